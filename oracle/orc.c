@@ -251,6 +251,7 @@ void orc_step(const orc_params *p, const double *f, double *fout, double *scratc
                 const double r = rho[s * n + k];
                 const double fx = Fx[s * n + k], fy = Fy[s * n + k];
                 const double tau = p->tau[s];
+                const double omega = 1.0 / tau; /* the factor 1/tau_s of Eq. 2 */
                 double vx = ux, vy = uy;
                 if (p->forcing == 0) {
                     /* Eq. 3: shifted velocity u' = u + tau_s F_s / rho_s. */
@@ -262,7 +263,7 @@ void orc_step(const orc_params *p, const double *f, double *fout, double *scratc
                 for (int i = 0; i < NQ; ++i) {
                     const double fi = f[fidx(p, s, i, y, x)];
                     /* Eq. 2: BGK relaxation towards the equilibrium. */
-                    double post = fi - (fi - feq[i]) / tau;
+                    double post = fi - omega * (fi - feq[i]);
                     if (p->forcing == 1) {
                         /* Guo source (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F_s */
                         double cu = CX[i] * ux + CY[i] * uy;
