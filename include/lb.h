@@ -1,0 +1,193 @@
+/*
+ * lb.h - C ABI of liblb.so, a gfx950 (MI355X) implementation of the
+ * two-component D2Q9 Shan-Chen lattice Boltzmann time step used by Tavares,
+ * Biferale, Sbragaglia and Mailybaev for 2D Rayleigh-Taylor turbulence
+ * ("Validation and application of the lattice Boltzmann algorithm for a
+ * turbulent immiscible Rayleigh-Taylor system"), with the energy-budget
+ * averages of its Sec. 3.
+ *
+ * Model (Sec. 2 of the paper)
+ *   populations f_i^s(x, t), s in {A, B}, D2Q9 velocities c_i, i = 0..8 in
+ *   the order (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1),
+ *   weights 4/9, 1/9 (axes), 1/36 (diagonals);
+ *   rho_s = sum_i f_i^s, common velocity weighted by 1/tau_s       (Eq. 1)
+ *   BGK relaxation towards f^eq(rho_s, u + tau_s F_s / rho_s)     (Eq. 2-3)
+ *   F_s = -G_AB rho_s sum_i w_i rho_sbar(x + c_i) c_i + rho_s g_s  (Eq. 5, 7)
+ *   periodic in x; bounce-back walls below row 0 and above row ny-1 (or
+ *   periodic in y for validation runs).
+ *
+ * Conventions
+ *   - Every function returns an int32 status: LB_OK (0) or a negative
+ *     LB_E* code; lb_last_error() then holds a message for the calling
+ *     thread.  No C++ exception crosses this interface.
+ *   - Device pointers are HIP device addresses on the current device;
+ *     host pointers are ordinary process memory.  Fields are [ny][nx]
+ *     row-major doubles (x fastest), populations [s][i][y][x] doubles.
+ *   - Time t counts completed steps.  Every output describes the
+ *     pre-collision state f(t) (after streaming), i.e. the left-hand side of
+ *     Eq. 2 at time t.
+ *   - Ownership: the caller owns the workspace (device memory of
+ *     lb_workspace_bytes bytes) and the HIP stream; both must outlive the
+ *     handle.  The library owns the host-side handle and any HIP graphs it
+ *     builds; lb_destroy releases them.  Inputs are copied during the call
+ *     that receives them.
+ *   - All work is enqueued on the handle's stream.  lb_step, lb_fields,
+ *     lb_get_populations and lb_set_populations never synchronise;
+ *     lb_diagnostics synchronises the stream before returning.
+ *   - A handle may be used from one host thread at a time.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define LB_OK 0
+#define LB_EINVAL (-1)      /* invalid argument (message names it) */
+#define LB_ENOMEM (-2)      /* workspace smaller than lb_workspace_bytes */
+#define LB_EHIP (-3)        /* a HIP runtime call failed (message holds its error string) */
+#define LB_ESTATE (-4)      /* handle unknown or already destroyed */
+#define LB_ENONFINITE (-5)  /* lb_diagnostics found a NaN or Inf density or velocity */
+
+/* Forcing scheme.  LB_FORCE_SHIFT is the paper's velocity shift inside the
+ * equilibrium (Eq. 2-3).  LB_FORCE_GUO is Guo's forcing (Guo, Zheng and Shi,
+ * 2002) with the common velocity (sum_s j_s + F/2)/rho in the equilibrium and
+ * the source (1 - 1/(2 tau_s)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F_s;
+ * it requires tau_A == tau_B. */
+#define LB_FORCE_SHIFT 0
+#define LB_FORCE_GUO 1
+
+/* Storage of the populations between steps.  Densities, the Shan-Chen force
+ * and every diagnostic sum are computed in FP64 in all modes.
+ *   LB_F64   FP64 storage, FP64 arithmetic throughout.
+ *   LB_F32   FP32 storage, FP32 collision.
+ *   LB_F16S  IEEE binary16 storage of q = (f_i - w_i rho0_s) * scale_{s,i}, FP32 collision.
+ *   LB_BF16S bfloat16 storage of the same shifted, scaled q, FP32 collision.
+ * scale_{s,i} is a power of two chosen at lb_init (see lb_member.rho0). */
+#define LB_F64 0
+#define LB_F32 1
+#define LB_F16S 2
+#define LB_BF16S 3
+
+/* Top/bottom boundary.  LB_WALLS: halfway bounce-back, no slip, walls half a
+ * link outside rows 0 and ny-1, neighbour density across a wall taken from
+ * the adjacent row (neutral wetting, G_sb = 0 of Eq. 6).  LB_PERIODIC_Y:
+ * periodic in y (validation runs only). */
+#define LB_WALLS 0
+#define LB_PERIODIC_Y 1
+
+#define LB_MAX_MEMBERS 64
+
+/* One independent realisation (ensemble member). */
+typedef struct lb_member {
+    int32_t nx, ny;          /* lattice size; nx >= 3, ny >= 3 */
+    double tau[2];           /* relaxation times tau_A, tau_B > 1/2 (Eq. 2) */
+    double G_AB;             /* Shan-Chen coupling of Eq. 5 (G > 0 repels A from B) */
+    double g[2][2];          /* body acceleration of each component, g[s] = {x, y};
+                                Eq. 7 is g[0] = {0, -g~}, g[1] = {0, +g~} */
+    const double *rhoA0;     /* host, [ny][nx]: initial densities; f(0) = w_i rho_s */
+    const double *rhoB0;
+    double rho0[2];          /* LB_F16S / LB_BF16S only: reference densities of the
+                                shift w_i rho0_s; 0 selects the mean initial density */
+} lb_member;
+
+typedef struct lb_config {
+    int32_t n_members;       /* 1 .. LB_MAX_MEMBERS */
+    const lb_member *members;
+    int32_t forcing;         /* LB_FORCE_* */
+    int32_t storage;         /* LB_F64 .. LB_BF16S, shared by all members */
+    int32_t bc_y;            /* LB_WALLS or LB_PERIODIC_Y */
+    int32_t diag_trim;       /* rows dropped at top and bottom for the averages of
+                                lb_diagnostics (the paper drops 10); >= 1 */
+    int32_t tile_x;          /* workgroup width in columns: 64, 128, 256 or 512;
+                                0 chooses by timing candidates at lb_init */
+    int32_t tile_h;          /* rows per tile (>= 1); 0 chooses with tile_x */
+    int32_t graph_chunk;     /* steps per captured HIP graph (even, >= 2);
+                                0 selects 100; negative disables graphs */
+} lb_config;
+
+/* Energy-budget averages at time t (Sec. 3, Eq. 15-18 and Eq. 22).  <.> is
+ * the mean over the trimmed domain D: rows [diag_trim, ny - diag_trim), all
+ * columns.  u is the hydrodynamic velocity (sum_s j_s + sum_s F_s / 2)/rho,
+ * y_j = j - (ny - 1)/2, derivatives are centred differences (x wraps). */
+typedef struct lb_diag {
+    int64_t t;
+    double mass[2];          /* sum of rho_A, rho_B over the whole lattice */
+    double Ek;               /* <rho |u|^2 / 2> */
+    double Ep;               /* -<y sum_s rho_s g_s,y>, equal to g~ <y phi> for Eq. 7 */
+    double buoyancy;         /* -<u . sum_s rho_s g_s>, equal to g~ <phi u_y>: dE_p/dt of Eq. 16 */
+    double omega2;           /* <omega^2>, omega = d_x u_y - d_y u_x; the viscous
+                                term of Eq. 22 is -eta * omega2 */
+    double umax;             /* max |u| over the whole lattice */
+    int32_t finite;          /* 1 if every density and velocity is finite */
+} lb_diag;
+
+typedef struct lb_handle lb_handle;
+
+/* Bytes of device workspace lb_init needs for cfg (0 if cfg is invalid;
+ * lb_last_error says why).  Every member's two population buffers, one
+ * [4][ny][nx] FP64 field buffer of the largest member and small tables. */
+size_t lb_workspace_bytes(const lb_config *cfg);
+
+/* Create a handle.  Copies the member table and the initial densities,
+ * lays out d_workspace (caller-owned, >= lb_workspace_bytes(cfg) bytes,
+ * 256-byte aligned), writes f(0) = w_i rho_s(0) for every member (Eq. 3 at
+ * rest), picks tile shapes (timing candidates if tile_x == 0, which advances
+ * no state) and returns the handle in *out at t = 0.  hip_stream is a
+ * hipStream_t (NULL = the null stream).  Synchronises the stream once. */
+int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip_stream,
+                lb_handle **out);
+
+/* Advance every member by n >= 0 time steps (Eq. 2), asynchronously on the
+ * handle's stream.  Full chunks of graph_chunk steps replay a HIP graph. */
+int32_t lb_step(lb_handle *h, int64_t n);
+
+/* Macroscopic fields of member m at the current time into caller device
+ * buffers of ny*nx doubles each: rho_A, rho_B and the hydrodynamic velocity
+ * (u_x, u_y).  Any pointer may be NULL to skip that field.  Asynchronous. */
+int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, double *d_ux,
+                  double *d_uy);
+
+/* Energy-budget averages of member m (see lb_diag) into *out (host), and,
+ * if phi_profile (host, ny doubles) is not NULL, the row means of
+ * phi = rho_A - rho_B.  Synchronises the stream.  Returns LB_ENONFINITE
+ * (after filling *out) if a density or velocity is not finite. */
+int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profile);
+
+/* Populations f(t) of member m, decoded to FP64, into a caller device buffer
+ * of 2*9*ny*nx doubles, layout [s][i][y][x].  Asynchronous. */
+int32_t lb_get_populations(lb_handle *h, int32_t m, double *d_f);
+
+/* Replace the state of member m by the populations d_f (device, layout as
+ * above) taken as f(t) at the current time.  Encoded to the storage mode.
+ * Asynchronous; d_f may be reused once the stream has passed this call. */
+int32_t lb_set_populations(lb_handle *h, int32_t m, const double *d_f);
+
+/* Completed steps (-1 if h is not a live handle). */
+int64_t lb_time(const lb_handle *h);
+
+/* Tile shape in use: workgroup width (columns) and rows per tile. */
+int32_t lb_tile_shape(const lb_handle *h, int32_t *tile_x, int32_t *tile_h);
+
+/* Storage scale of member m for the 16-bit modes: scale[s*9 + i] receives
+ * scale_{s,i} and shift[s*9 + i] receives w_i rho0_s (host arrays of 18;
+ * either may be NULL).  In LB_F64 / LB_F32 the scales are 1 and shifts 0. */
+int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *shift);
+
+/* Destroy a handle: waits for its stream, frees graphs and host state.  The
+ * workspace stays with the caller.  Later calls with h return LB_ESTATE. */
+int32_t lb_destroy(lb_handle *h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

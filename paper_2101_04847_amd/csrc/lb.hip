@@ -1,0 +1,666 @@
+// Host runtime of liblb.so: the C ABI declared in include/lb.h.
+//
+// Responsibilities: validate configurations, lay out the caller's workspace,
+// write the initial state, choose tile shapes (by timing candidates on the
+// caller's stream), build HIP graphs of step chunks, dispatch the templated
+// gfx950 kernels of lb_kernels.hpp and map HIP failures to LB_EHIP.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "lb_kernels.hpp"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(LB_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage)
+{
+    switch (storage) {
+        case LB_F64: return 8;
+        case LB_F32: return 4;
+        default: return 2;
+    }
+}
+
+int64_t pitch_of(int nx) { return (int64_t)align_up((size_t)nx, 64); }
+
+// ---------------------------------------------------------------------------
+// Kernel dispatch tables.
+using StepFn = void (*)(const Member *, int, int64_t, int64_t, int, FieldOut);
+using ScatterFn = void (*)(const Member *, int, const double *, const double *, const double *, int, int);
+using GatherFn = void (*)(const Member *, int, double *, int);
+
+constexpr int TX_VALUES[4] = {64, 128, 256, 512};
+int tx_index(int tx)
+{
+    for (int k = 0; k < 4; ++k)
+        if (TX_VALUES[k] == tx) return k;
+    return -1;
+}
+
+template <int ST, int F, int B, bool FIELDS>
+StepFn step_for_tx(int k)
+{
+    switch (k) {
+        case 0: return (StepFn)k_step<ST, F, B, 64, FIELDS>;
+        case 1: return (StepFn)k_step<ST, F, B, 128, FIELDS>;
+        case 2: return (StepFn)k_step<ST, F, B, 256, FIELDS>;
+        default: return (StepFn)k_step<ST, F, B, 512, FIELDS>;
+    }
+}
+
+template <int ST, bool FIELDS>
+StepFn step_for(int forcing, int bc, int k)
+{
+    if (forcing == LB_FORCE_SHIFT)
+        return bc == LB_WALLS ? step_for_tx<ST, FORCE_SHIFT, BC_WALLS, FIELDS>(k)
+                              : step_for_tx<ST, FORCE_SHIFT, BC_PERIODIC, FIELDS>(k);
+    return bc == LB_WALLS ? step_for_tx<ST, FORCE_GUO, BC_WALLS, FIELDS>(k)
+                          : step_for_tx<ST, FORCE_GUO, BC_PERIODIC, FIELDS>(k);
+}
+
+StepFn pick_step(int storage, int forcing, int bc, int k, bool fields)
+{
+    if (fields) {
+        // the field pass does not depend on the forcing scheme
+        switch (storage) {
+            case LB_F64: return step_for<ST_F64, true>(LB_FORCE_SHIFT, bc, k);
+            case LB_F32: return step_for<ST_F32, true>(LB_FORCE_SHIFT, bc, k);
+            case LB_F16S: return step_for<ST_F16S, true>(LB_FORCE_SHIFT, bc, k);
+            default: return step_for<ST_BF16S, true>(LB_FORCE_SHIFT, bc, k);
+        }
+    }
+    switch (storage) {
+        case LB_F64: return step_for<ST_F64, false>(forcing, bc, k);
+        case LB_F32: return step_for<ST_F32, false>(forcing, bc, k);
+        case LB_F16S: return step_for<ST_F16S, false>(forcing, bc, k);
+        default: return step_for<ST_BF16S, false>(forcing, bc, k);
+    }
+}
+
+template <int ST>
+ScatterFn scatter_for(int bc) { return bc == LB_WALLS ? k_scatter<ST, BC_WALLS> : k_scatter<ST, BC_PERIODIC>; }
+template <int ST>
+GatherFn gather_for(int bc) { return bc == LB_WALLS ? k_gather<ST, BC_WALLS> : k_gather<ST, BC_PERIODIC>; }
+
+ScatterFn pick_scatter(int storage, int bc)
+{
+    switch (storage) {
+        case LB_F64: return scatter_for<ST_F64>(bc);
+        case LB_F32: return scatter_for<ST_F32>(bc);
+        case LB_F16S: return scatter_for<ST_F16S>(bc);
+        default: return scatter_for<ST_BF16S>(bc);
+    }
+}
+
+GatherFn pick_gather(int storage, int bc)
+{
+    switch (storage) {
+        case LB_F64: return gather_for<ST_F64>(bc);
+        case LB_F32: return gather_for<ST_F32>(bc);
+        case LB_F16S: return gather_for<ST_F16S>(bc);
+        default: return gather_for<ST_BF16S>(bc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout.
+struct Layout {
+    size_t members;                 // Member table
+    std::vector<size_t> fbuf[2];    // per member, buffer 0 and 1
+    size_t fields;                  // [4][ny][nx] FP64 of the largest member
+    size_t part;                    // [ny_max][RED_NQ] FP64 row partials
+    size_t red;                     // [RED_NQ] FP64 results + profile [ny_max]
+    size_t total;
+};
+
+bool build_layout(const lb_config *c, Layout &L)
+{
+    size_t off = 0;
+    L.members = off;
+    off = align_up(off + sizeof(Member) * (size_t)c->n_members, ALIGN);
+    int64_t max_sites = 0, max_ny = 0;
+    const size_t eb = elem_bytes(c->storage);
+    for (int b = 0; b < 2; ++b) L.fbuf[b].resize(c->n_members);
+    for (int m = 0; m < c->n_members; ++m) {
+        const lb_member &mm = c->members[m];
+        const size_t bytes = (size_t)2 * NQ * (size_t)mm.ny * (size_t)pitch_of(mm.nx) * eb;
+        for (int b = 0; b < 2; ++b) {
+            L.fbuf[b][m] = off;
+            off = align_up(off + bytes, ALIGN);
+        }
+        max_sites = std::max<int64_t>(max_sites, (int64_t)mm.nx * mm.ny);
+        max_ny = std::max<int64_t>(max_ny, mm.ny);
+    }
+    L.fields = off;
+    off = align_up(off + (size_t)4 * (size_t)max_sites * sizeof(double), ALIGN);
+    L.part = off;
+    off = align_up(off + (size_t)max_ny * RED_NQ * sizeof(double), ALIGN);
+    L.red = off;
+    off = align_up(off + ((size_t)RED_NQ + (size_t)max_ny) * sizeof(double), ALIGN);
+    L.total = off;
+    return true;
+}
+
+int32_t validate(const lb_config *c)
+{
+    if (!c) return fail(LB_EINVAL, "config is NULL");
+    if (c->n_members < 1 || c->n_members > LB_MAX_MEMBERS)
+        return fail(LB_EINVAL, "n_members = %d outside [1, %d]", c->n_members, LB_MAX_MEMBERS);
+    if (!c->members) return fail(LB_EINVAL, "members is NULL");
+    if (c->forcing != LB_FORCE_SHIFT && c->forcing != LB_FORCE_GUO)
+        return fail(LB_EINVAL, "forcing = %d is not LB_FORCE_SHIFT or LB_FORCE_GUO", c->forcing);
+    if (c->storage < LB_F64 || c->storage > LB_BF16S) return fail(LB_EINVAL, "storage = %d out of range", c->storage);
+    if (c->bc_y != LB_WALLS && c->bc_y != LB_PERIODIC_Y) return fail(LB_EINVAL, "bc_y = %d out of range", c->bc_y);
+    if (c->diag_trim < 1) return fail(LB_EINVAL, "diag_trim = %d must be >= 1", c->diag_trim);
+    if (c->tile_x != 0 && tx_index(c->tile_x) < 0)
+        return fail(LB_EINVAL, "tile_x = %d must be 0, 64, 128, 256 or 512", c->tile_x);
+    if (c->tile_h < 0) return fail(LB_EINVAL, "tile_h = %d must be >= 0", c->tile_h);
+    if (c->graph_chunk > 0 && (c->graph_chunk % 2 != 0))
+        return fail(LB_EINVAL, "graph_chunk = %d must be even", c->graph_chunk);
+    for (int m = 0; m < c->n_members; ++m) {
+        const lb_member &mm = c->members[m];
+        if (mm.nx < 3 || mm.ny < 3) return fail(LB_EINVAL, "member %d: nx = %d, ny = %d must be >= 3", m, mm.nx, mm.ny);
+        if ((int64_t)mm.nx * mm.ny > ((int64_t)1 << 31))
+            return fail(LB_EINVAL, "member %d: %d x %d sites exceed 2^31", m, mm.nx, mm.ny);
+        for (int s = 0; s < 2; ++s)
+            if (!(mm.tau[s] > 0.5) || !std::isfinite(mm.tau[s]))
+                return fail(LB_EINVAL, "member %d: tau[%d] = %g must be finite and > 1/2", m, s, mm.tau[s]);
+        if (c->forcing == LB_FORCE_GUO && mm.tau[0] != mm.tau[1])
+            return fail(LB_EINVAL, "member %d: Guo forcing needs tau_A == tau_B", m);
+        if (!std::isfinite(mm.G_AB)) return fail(LB_EINVAL, "member %d: G_AB is not finite", m);
+        for (int s = 0; s < 2; ++s)
+            for (int a = 0; a < 2; ++a)
+                if (!std::isfinite(mm.g[s][a])) return fail(LB_EINVAL, "member %d: g[%d][%d] is not finite", m, s, a);
+        if (!mm.rhoA0 || !mm.rhoB0) return fail(LB_EINVAL, "member %d: initial densities are NULL", m);
+        if (mm.ny <= 2 * c->diag_trim) return fail(LB_EINVAL, "member %d: ny = %d leaves no rows after trimming %d", m, mm.ny, c->diag_trim);
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+struct lb_handle {
+    lb_config cfg{};
+    std::vector<lb_member> mem;     // parameters (host pointers cleared after init)
+    std::vector<Member> dm;         // device table mirror
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;  // private stream used only to record graphs
+    char *ws = nullptr;
+    Layout L;
+    int64_t t = 0;
+    int cur = 0;
+    int tile_x = 0, tile_h = 0;
+    int64_t n_items = 0;
+    int chunk = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraph_t graph_src[2] = {nullptr, nullptr};
+    int device = 0;
+};
+
+namespace {
+
+std::mutex g_live_mu;
+std::set<const lb_handle *> g_live;
+
+bool is_live(const lb_handle *h)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return h && g_live.count(h) > 0;
+}
+
+Member *dev_members(lb_handle *h) { return (Member *)(h->ws + h->L.members); }
+
+// Number of tiles and their assignment to work items for a given shape.
+void plan_tiles(lb_handle *h, int tx, int th)
+{
+    int64_t item = 0;
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        Member &M = h->dm[m];
+        M.tiles_x = (M.nx + tx - 1) / tx;
+        M.tile_h = std::min(th, M.ny);
+        M.tiles_y = (M.ny + M.tile_h - 1) / M.tile_h;
+        M.item_begin = item;
+        item += (int64_t)M.tiles_x * M.tiles_y;
+        M.item_end = item;
+    }
+    h->n_items = item;
+    h->tile_x = tx;
+    h->tile_h = th;
+}
+
+int32_t upload_members(lb_handle *h)
+{
+    HIP_TRY(hipMemcpyAsync(dev_members(h), h->dm.data(), sizeof(Member) * h->dm.size(), hipMemcpyHostToDevice, h->stream));
+    return LB_OK;
+}
+
+int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
+{
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(h->tile_x), false);
+    const FieldOut none{nullptr, nullptr, nullptr, nullptr};
+    for (int64_t k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items), dim3(h->tile_x), 0, s, (const Member *)dev_members(h),
+                           (int)h->dm.size(), (int64_t)0, h->n_items, cur, none);
+        cur ^= 1;
+    }
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+void free_graphs(lb_handle *h)
+{
+    for (int p = 0; p < 2; ++p) {
+        if (h->graph[p]) hipGraphExecDestroy(h->graph[p]);
+        if (h->graph_src[p]) hipGraphDestroy(h->graph_src[p]);
+        h->graph[p] = nullptr;
+        h->graph_src[p] = nullptr;
+    }
+}
+
+// Record one graph per starting buffer parity: chunk launches of the step.
+int32_t build_graphs(lb_handle *h)
+{
+    free_graphs(h);
+    if (h->chunk <= 0) return LB_OK;
+    for (int p = 0; p < 2; ++p) {
+        HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+        int c = p;
+        int32_t rc = launch_steps(h, h->capture, h->chunk, c);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->capture, &g);
+        if (rc != LB_OK) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        h->graph_src[p] = g;
+        HIP_TRY(hipGraphInstantiate(&h->graph[p], g, nullptr, nullptr, 0));
+    }
+    return LB_OK;
+}
+
+// Time `reps` steps that read the current buffer and write the other one
+// (state unchanged) with tile shape (tx, th); returns milliseconds per step.
+int32_t time_shape(lb_handle *h, int tx, int th, int reps, float &ms)
+{
+    plan_tiles(h, tx, th);
+    int32_t rc = upload_members(h);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(tx), false);
+    const FieldOut none{nullptr, nullptr, nullptr, nullptr};
+    auto once = [&]() {
+        hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items), dim3(tx), 0, h->stream, (const Member *)dev_members(h),
+                           (int)h->dm.size(), (int64_t)0, h->n_items, h->cur, none);
+    };
+    once();  // warm-up
+    HIP_TRY(hipEventRecord(a, h->stream));
+    for (int r = 0; r < reps; ++r) once();
+    HIP_TRY(hipEventRecord(b, h->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    ms /= (float)reps;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return LB_OK;
+}
+
+int32_t choose_tiles(lb_handle *h)
+{
+    const lb_config &c = h->cfg;
+    int64_t max_nx = 0, sites = 0;
+    for (auto &M : h->dm) {
+        max_nx = std::max<int64_t>(max_nx, M.nx);
+        sites += (int64_t)M.nx * M.ny;
+    }
+    if (c.tile_x != 0) {
+        int th = c.tile_h > 0 ? c.tile_h : 64;
+        plan_tiles(h, c.tile_x, th);
+        return upload_members(h);
+    }
+    // candidates: widths no wider than the lattice needs, heights 16..256
+    std::vector<std::pair<int, int>> cand;
+    for (int tx : {64, 128, 256, 512}) {
+        if (tx > 64 && tx / 2 >= max_nx) continue;
+        for (int th : {16, 32, 64, 128, 256}) {
+            if (c.tile_h > 0 && th != c.tile_h) continue;
+            cand.push_back({tx, th});
+        }
+    }
+    if (c.tile_h > 0 && cand.empty()) cand.push_back({64, c.tile_h});
+    // timing repetitions: about 50 ms of work per candidate at ~20 GLUPS
+    int reps = (int)std::max<int64_t>(2, std::min<int64_t>(20, (int64_t)1e9 / std::max<int64_t>(sites, 1)));
+    float best = 1e30f;
+    std::pair<int, int> best_shape = cand.front();
+    for (auto &sh : cand) {
+        float ms = 0;
+        int32_t rc = time_shape(h, sh.first, sh.second, reps, ms);
+        if (rc) return rc;
+        if (ms < best) {
+            best = ms;
+            best_shape = sh;
+        }
+    }
+    plan_tiles(h, best_shape.first, best_shape.second);
+    return upload_members(h);
+}
+
+// Per-member storage scales for the 16-bit modes.
+void set_scales(const lb_config *c, const lb_member &mm, Member &M)
+{
+    const int64_t n = (int64_t)mm.nx * mm.ny;
+    for (int s = 0; s < 2; ++s) {
+        const double *rho = s == 0 ? mm.rhoA0 : mm.rhoB0;
+        double ref = mm.rho0[s];
+        double lo = rho[0], hi = rho[0], sum = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            lo = std::min(lo, rho[k]);
+            hi = std::max(hi, rho[k]);
+            sum += rho[k];
+        }
+        if (!(ref > 0)) ref = sum / (double)n;
+        for (int i = 0; i < NQ; ++i) {
+            M.shift[s][i] = 0.0f;
+            M.scale[s][i] = 1.0f;
+            M.iscale[s][i] = 1.0f;
+            if (c->storage == LB_F16S || c->storage == LB_BF16S) {
+                const double w = wgt(i);
+                M.shift[s][i] = (float)(w * ref);
+                // largest excursion |f_i - w_i rho0| expected: the density
+                // spread plus headroom for flow (factor 2).  binary16 keeps
+                // q below 2^14 to stay far from its 65504 limit; bfloat16
+                // has the FP32 exponent range and needs no scale.
+                double span = 2.0 * w * std::max(std::fabs(hi - ref), std::fabs(ref - lo)) + 1e-30;
+                int e = 0;
+                if (c->storage == LB_F16S) e = (int)std::floor(std::log2(16384.0 / span));
+                e = std::max(-60, std::min(60, e));
+                M.scale[s][i] = std::ldexp(1.0f, e);
+                M.iscale[s][i] = std::ldexp(1.0f, -e);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_workspace_bytes(const lb_config *cfg)
+{
+    if (validate(cfg) != LB_OK) return 0;
+    Layout L;
+    build_layout(cfg, L);
+    return L.total;
+}
+
+int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip_stream, lb_handle **out)
+{
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int32_t rc = validate(cfg);
+    if (rc) return rc;
+    if (!d_workspace) return fail(LB_EINVAL, "workspace is NULL");
+    if (((uintptr_t)d_workspace) % ALIGN) return fail(LB_EINVAL, "workspace is not %zu-byte aligned", ALIGN);
+    Layout L;
+    build_layout(cfg, L);
+    if (bytes < L.total) return fail(LB_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, L.total);
+
+    lb_handle *h = new (std::nothrow) lb_handle();
+    if (!h) return fail(LB_EINVAL, "host allocation failed");
+    h->cfg = *cfg;
+    h->mem.assign(cfg->members, cfg->members + cfg->n_members);
+    h->cfg.members = nullptr;
+    h->stream = (hipStream_t)hip_stream;
+    h->ws = (char *)d_workspace;
+    h->L = L;
+    h->chunk = cfg->graph_chunk == 0 ? 100 : (cfg->graph_chunk < 0 ? 0 : cfg->graph_chunk);
+
+    auto bail = [&](int32_t code) {
+        free_graphs(h);
+        if (h->capture) hipStreamDestroy(h->capture);
+        delete h;
+        return code;
+    };
+    if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(LB_EHIP, "hipGetDevice failed"));
+    if (hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(LB_EHIP, "hipStreamCreateWithFlags failed"));
+
+    h->dm.resize(cfg->n_members);
+    for (int m = 0; m < cfg->n_members; ++m) {
+        const lb_member &mm = cfg->members[m];
+        Member &M = h->dm[m];
+        std::memset(&M, 0, sizeof M);
+        M.nx = mm.nx;
+        M.ny = mm.ny;
+        M.pitch = (int32_t)pitch_of(mm.nx);
+        M.plane = (int64_t)mm.ny * M.pitch;
+        M.f[0] = h->ws + L.fbuf[0][m];
+        M.f[1] = h->ws + L.fbuf[1][m];
+        for (int s = 0; s < 2; ++s) {
+            M.tau[s] = mm.tau[s];
+            M.itau[s] = 1.0 / mm.tau[s];
+            M.g[s][0] = mm.g[s][0];
+            M.g[s][1] = mm.g[s][1];
+        }
+        M.G = mm.G_AB;
+        set_scales(cfg, mm, M);
+    }
+    plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, cfg->tile_h ? cfg->tile_h : 64);
+    if ((rc = upload_members(h))) return bail(rc);
+
+    // initial state f(0) = w_i rho_s(0), written as the pre-streamed buffer
+    double *stage = (double *)(h->ws + L.fields);
+    for (int m = 0; m < cfg->n_members; ++m) {
+        const lb_member &mm = cfg->members[m];
+        const size_t n = (size_t)mm.nx * mm.ny;
+        if (hipMemcpyAsync(stage, mm.rhoA0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess ||
+            hipMemcpyAsync(stage + n, mm.rhoB0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+            return bail(fail(LB_EHIP, "copy of initial densities failed"));
+        ScatterFn fn = pick_scatter(cfg->storage, cfg->bc_y);
+        const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, h->stream, (const Member *)dev_members(h), m,
+                           (const double *)nullptr, (const double *)stage, (const double *)(stage + n), 1, 0);
+        if (hipGetLastError() != hipSuccess) return bail(fail(LB_EHIP, "initial scatter launch failed"));
+        // the staging area is reused by the next member only after this one is written
+        if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(LB_EHIP, "stream synchronisation failed"));
+    }
+    for (auto &mm : h->mem) {
+        mm.rhoA0 = nullptr;
+        mm.rhoB0 = nullptr;
+    }
+    if ((rc = choose_tiles(h))) return bail(rc);
+    if ((rc = build_graphs(h))) return bail(rc);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(LB_EHIP, "stream synchronisation failed"));
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return LB_OK;
+}
+
+int32_t lb_step(lb_handle *h, int64_t n)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (n < 0) return fail(LB_EINVAL, "n = %lld must be >= 0", (long long)n);
+    int64_t left = n;
+    if (h->chunk > 0) {
+        while (left >= h->chunk) {
+            HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
+            left -= h->chunk;  // chunk is even: the buffer parity is unchanged
+        }
+    }
+    int c = h->cur;
+    int32_t rc = launch_steps(h, h->stream, left, c);
+    if (rc) return rc;
+    h->cur = c;
+    h->t += n;
+    return LB_OK;
+}
+
+int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, double *d_ux, double *d_uy)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    const Member &M = h->dm[m];
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(h->tile_x), true);
+    FieldOut fo{d_rhoA, d_rhoB, d_ux, d_uy};
+    const int64_t n_items = M.item_end - M.item_begin;
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_items), dim3(h->tile_x), 0, h->stream, (const Member *)dev_members(h),
+                       (int)h->dm.size(), M.item_begin, n_items, h->cur, fo);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profile)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    const Member &M = h->dm[m];
+    const lb_member &mm = h->mem[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    double *fld = (double *)(h->ws + h->L.fields);
+    int32_t rc = lb_fields(h, m, fld, fld + n, fld + 2 * n, fld + 3 * n);
+    if (rc) return rc;
+    double *part = (double *)(h->ws + h->L.part);
+    double *red = (double *)(h->ws + h->L.red);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(M.ny), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, mm.g[0][0], mm.g[0][1], mm.g[1][0], mm.g[1][1], part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, M.nx, M.ny, red,
+                       red + RED_NQ);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> host((size_t)RED_NQ + (phi_profile ? (size_t)M.ny : 0));
+    HIP_TRY(hipMemcpyAsync(host.data(), red, host.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double nd = (double)M.nx * (double)(M.ny - 2 * h->cfg.diag_trim);
+    out->t = h->t;
+    out->mass[0] = host[0];
+    out->mass[1] = host[1];
+    out->Ek = host[3] / nd;
+    out->Ep = host[4] / nd;
+    out->buoyancy = host[5] / nd;
+    out->omega2 = host[6] / nd;
+    out->umax = host[7];
+    out->finite = host[8] == 0.0 ? 1 : 0;
+    if (phi_profile) std::memcpy(phi_profile, host.data() + RED_NQ, (size_t)M.ny * sizeof(double));
+    if (!out->finite) return fail(LB_ENONFINITE, "member %d: %.0f non-finite densities or velocities at t = %lld", m,
+                                  host[8], (long long)h->t);
+    return LB_OK;
+}
+
+int32_t lb_get_populations(lb_handle *h, int32_t m, double *d_f)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!d_f) return fail(LB_EINVAL, "d_f is NULL");
+    const Member &M = h->dm[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(pick_gather(h->cfg.storage, h->cfg.bc_y), dim3(grid), dim3(256), 0, h->stream,
+                       (const Member *)dev_members(h), m, d_f, h->cur);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int32_t lb_set_populations(lb_handle *h, int32_t m, const double *d_f)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!d_f) return fail(LB_EINVAL, "d_f is NULL");
+    const Member &M = h->dm[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(pick_scatter(h->cfg.storage, h->cfg.bc_y), dim3(grid), dim3(256), 0, h->stream,
+                       (const Member *)dev_members(h), m, d_f, (const double *)nullptr, (const double *)nullptr, 0,
+                       h->cur);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int64_t lb_time(const lb_handle *h)
+{
+    if (!is_live(h)) {
+        fail(LB_ESTATE, "handle is not live");
+        return -1;
+    }
+    return h->t;
+}
+
+int32_t lb_tile_shape(const lb_handle *h, int32_t *tile_x, int32_t *tile_h)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (tile_x) *tile_x = h->tile_x;
+    if (tile_h) *tile_h = h->tile_h;
+    return LB_OK;
+}
+
+int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *shift)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < NQ; ++i) {
+            if (scale) scale[s * NQ + i] = h->dm[m].scale[s][i];
+            if (shift) shift[s * NQ + i] = h->dm[m].shift[s][i];
+        }
+    return LB_OK;
+}
+
+int32_t lb_destroy(lb_handle *h)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        if (!h || !g_live.count(h)) return fail(LB_ESTATE, "handle is not live");
+        g_live.erase(h);
+    }
+    hipError_t e = hipStreamSynchronize(h->stream);
+    free_graphs(h);
+    if (h->capture) hipStreamDestroy(h->capture);
+    delete h;
+    if (e != hipSuccess) return fail(LB_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+}  // extern "C"

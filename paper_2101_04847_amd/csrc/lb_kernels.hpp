@@ -1,0 +1,589 @@
+// gfx950 kernels of the two-component D2Q9 Shan-Chen lattice Boltzmann step.
+//
+// Method (paper Sec. 2): per component s, rho_s = sum_i f_i^s (Eq. 1);
+// Shan-Chen force F_s = -G rho_s sum_i w_i rho_sbar(x + c_i) c_i (Eq. 5) plus
+// buoyancy rho_s g_s (Eq. 7); common velocity weighted by 1/tau_s (Eq. 1);
+// BGK relaxation towards f^eq(rho_s, u + tau_s F_s / rho_s) (Eq. 2-3) or Guo
+// forcing; streaming with periodic x and halfway bounce-back walls.
+//
+// Storage: buffer[s][i][y][pitch] per member, x fastest, pitch a multiple of
+// 64 elements.  A buffer holds post-collision populations f*(t-1); the
+// pre-collision state f(t) is obtained by PULLING: f_i(x) = f*_i(x - c_i),
+// or f*_opp(i)(x) where x - c_i lies beyond a wall.
+//
+// The step kernel is HBM-bound (no dense contraction, so no MFMA): one
+// workgroup owns TX columns and marches up a band of H rows.  For each row it
+// pulls the 18 populations of the next row (kept in registers until that row
+// is collided), writes rho_A, rho_B of that row into a 4-row LDS ring, and
+// after one barrier evaluates the force of the current row from the ring
+// (8 neighbours of both components), collides and stores.  The two halo
+// columns of the ring are pulled by lanes 0 and 1; the halo rows above and
+// below the band cost 2/H extra row reads.  Every population is read once
+// and written once per step apart from those halos.
+//
+// In the FP64 mode every expression is evaluated in the order of the
+// definitions (sums over i in index order, no contraction), so the step is
+// reproducible bit for bit by a plain CPU implementation of the same
+// equations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lb_internal.hpp"
+
+namespace lbk {
+
+// ---------------------------------------------------------------------------
+// D2Q9 lattice (Sec. 2): velocities in the order
+// 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1)
+// and the weights fixed by the isotropy conditions of Eq. 4.
+__host__ __device__ constexpr int cx(int i) { return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0; }
+__host__ __device__ constexpr int cy(int i) { return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0; }
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 5 + 2) % 4) + 5); }
+__host__ __device__ constexpr double wgt(int i) { return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
+static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
+
+// ---------------------------------------------------------------------------
+// Storage traits: element type T in memory, arithmetic type C of the collision.
+template <int ST> struct Tr;
+
+template <> struct Tr<ST_F64> {
+    using T = double;
+    using C = double;
+    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
+    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
+};
+
+template <> struct Tr<ST_F32> {
+    using T = float;
+    using C = float;
+    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
+    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
+};
+
+// IEEE binary16 holding q = (f - shift) * scale; f = shift + q / scale.
+template <> struct Tr<ST_F16S> {
+    using T = _Float16;
+    using C = float;
+    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return shift + (float)v * iscale; }
+    static __device__ __forceinline__ T enc(C v, float shift, float scale) { return (_Float16)((v - shift) * scale); }
+};
+
+// bfloat16 (kept as raw 16-bit patterns) holding the same shifted, scaled q.
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float x)
+{
+    // round to nearest even on the 16 dropped mantissa bits; NaN stays NaN
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <> struct Tr<ST_BF16S> {
+    using T = uint16_t;
+    using C = float;
+    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return shift + bf16_to_f32(v) * iscale; }
+    static __device__ __forceinline__ T enc(C v, float shift, float scale) { return f32_to_bf16((v - shift) * scale); }
+};
+
+// ---------------------------------------------------------------------------
+// Pull the 18 pre-collision populations f(t) of column c, row y from the
+// post-collision buffer src (streaming with periodic x, and either halfway
+// bounce-back walls or periodic y).
+template <int ST, int BCY>
+__device__ __forceinline__ void pull_site(const typename Tr<ST>::T *__restrict__ src, const Member &M,
+                                          int y, int c, typename Tr<ST>::C (&f)[2][NQ])
+{
+    using Q = Tr<ST>;
+    const int nx = M.nx, ny = M.ny;
+    const int64_t plane = M.plane, pitch = M.pitch;
+    const int cm = (c == 0) ? nx - 1 : c - 1;  // source column for c_x = +1
+    const int cp = (c == nx - 1) ? 0 : c + 1;  // source column for c_x = -1
+    int ym = y - 1, yp = y + 1;                 // source rows for c_y = +1 / -1
+    bool bb_lo = false, bb_hi = false;
+    if (BCY == BC_PERIODIC) {
+        if (ym < 0) ym = ny - 1;
+        if (yp >= ny) yp = 0;
+    } else {
+        bb_lo = ym < 0;
+        bb_hi = yp >= ny;
+    }
+    const int64_t r0 = (int64_t)y * pitch;
+    const int64_t rm = (int64_t)ym * pitch;
+    const int64_t rp = (int64_t)yp * pitch;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const typename Q::T *b = src + (int64_t)s * NQ * plane;
+        // offsets of the nine sources (bounce-back: same site, reversed velocity)
+        const int64_t o0 = 0 * plane + r0 + c;
+        const int64_t o1 = 1 * plane + r0 + cm;
+        const int64_t o3 = 3 * plane + r0 + cp;
+        const int64_t o2 = bb_lo ? 4 * plane + r0 + c : 2 * plane + rm + c;
+        const int64_t o5 = bb_lo ? 7 * plane + r0 + c : 5 * plane + rm + cm;
+        const int64_t o6 = bb_lo ? 8 * plane + r0 + c : 6 * plane + rm + cp;
+        const int64_t o4 = bb_hi ? 2 * plane + r0 + c : 4 * plane + rp + c;
+        const int64_t o7 = bb_hi ? 5 * plane + r0 + c : 7 * plane + rp + cp;
+        const int64_t o8 = bb_hi ? 6 * plane + r0 + c : 8 * plane + rp + cm;
+        f[s][0] = Q::dec(b[o0], M.shift[s][0], M.iscale[s][0]);
+        f[s][1] = Q::dec(b[o1], M.shift[s][1], M.iscale[s][1]);
+        f[s][2] = Q::dec(b[o2], M.shift[s][2], M.iscale[s][2]);
+        f[s][3] = Q::dec(b[o3], M.shift[s][3], M.iscale[s][3]);
+        f[s][4] = Q::dec(b[o4], M.shift[s][4], M.iscale[s][4]);
+        f[s][5] = Q::dec(b[o5], M.shift[s][5], M.iscale[s][5]);
+        f[s][6] = Q::dec(b[o6], M.shift[s][6], M.iscale[s][6]);
+        f[s][7] = Q::dec(b[o7], M.shift[s][7], M.iscale[s][7]);
+        f[s][8] = Q::dec(b[o8], M.shift[s][8], M.iscale[s][8]);
+    }
+}
+
+// Eq. 1: rho_s = sum_i f_i^s in index order, in FP64.
+template <class C>
+__device__ __forceinline__ double density(const C (&f)[NQ])
+{
+    double r = (double)f[0];
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) r += (double)f[i];
+    return r;
+}
+
+// j_s = sum_i f_i^s c_i in index order (terms with c = 0 add nothing).
+template <class C>
+__device__ __forceinline__ void momentum(const C (&f)[NQ], double &jx, double &jy)
+{
+    jx = (double)f[1];
+    jx -= (double)f[3];
+    jx += (double)f[5];
+    jx -= (double)f[6];
+    jx -= (double)f[7];
+    jx += (double)f[8];
+    jy = (double)f[2];
+    jy -= (double)f[4];
+    jy += (double)f[5];
+    jy += (double)f[6];
+    jy -= (double)f[7];
+    jy -= (double)f[8];
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.  FIELDS = false: collide and store f*(t) into the other
+// buffer.  FIELDS = true: write rho_A, rho_B and the hydrodynamic velocity of
+// f(t) instead (no state change).  Work items are tiles of TX columns by
+// tile_h rows, numbered per member; a launch covers items [item0, item0 + n).
+template <int ST, int FORCING, int BCY, int TX, bool FIELDS>
+__global__ void __launch_bounds__(TX)
+k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur,
+       FieldOut fo)
+{
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    using C = typename Q::C;
+    constexpr int LW = TX + 2;                  // ring row: TX columns plus two halo columns
+    __shared__ double ring[4][2][LW];           // rho_A, rho_B of four consecutive rows
+
+    const int lane = threadIdx.x;
+    for (int64_t item = item0 + blockIdx.x; item < item0 + n_items; item += gridDim.x) {
+        int m = 0;
+        while (m + 1 < n_members && members[m].item_end <= item) ++m;
+        const Member &M = members[m];
+        const int nx = M.nx, ny = M.ny;
+        const int64_t local = item - M.item_begin;
+        const int tx = (int)(local % M.tiles_x);
+        const int ty = (int)(local / M.tiles_x);
+        const int x0 = tx * TX;
+        const int y0 = ty * M.tile_h;
+        const int nrows = min(M.tile_h, ny - y0);
+        const T *__restrict__ src = (const T *)M.f[cur];
+        T *__restrict__ dst = (T *)M.f[cur ^ 1];
+
+        const int x = x0 + lane;
+        const bool active = x < nx;
+        // column pulled by this lane: its own, or column 0 (periodic image)
+        // for the first lane past the right edge of the lattice
+        const int col = active ? x : (x == nx ? 0 : -1);
+        // halo columns of the ring: lane 0 pulls x0 - 1, lane 1 pulls x0 + TX
+        int hcol = -1;
+        if (lane == 0) hcol = (x0 == 0) ? nx - 1 : x0 - 1;
+        if (lane == 1 && x0 + TX <= nx) hcol = (x0 + TX == nx) ? 0 : x0 + TX;
+        const int hent = (lane == 0) ? 0 : LW - 1;
+
+        C cur_f[2][NQ], nxt_f[2][NQ];
+        double rho_c[2] = {0.0, 0.0};   // rho of this lane's column at the current row
+        double rho_h[2] = {0.0, 0.0};   // rho of the halo column at the last row fetched
+
+        // --- prologue: row y0 (full) and row y0 - 1 (densities only)
+        if (col >= 0) {
+            pull_site<ST, BCY>(src, M, y0, col, cur_f);
+            rho_c[0] = density(cur_f[0]);
+            rho_c[1] = density(cur_f[1]);
+            ring[1][0][lane + 1] = rho_c[0];
+            ring[1][1][lane + 1] = rho_c[1];
+        }
+        if (hcol >= 0) {
+            C hf[2][NQ];
+            pull_site<ST, BCY>(src, M, y0, hcol, hf);
+            rho_h[0] = density(hf[0]);
+            rho_h[1] = density(hf[1]);
+            ring[1][0][hent] = rho_h[0];
+            ring[1][1][hent] = rho_h[1];
+        }
+        {
+            // row below the band: a real row, the periodic image of the top
+            // row, or (walls) the mirror of row 0
+            const bool mirror = (y0 == 0) && (BCY == BC_WALLS);
+            const int yb = (y0 == 0) ? ny - 1 : y0 - 1;
+            if (col >= 0) {
+                double r0 = rho_c[0], r1 = rho_c[1];
+                if (!mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, yb, col, hf);
+                    r0 = density(hf[0]);
+                    r1 = density(hf[1]);
+                }
+                ring[0][0][lane + 1] = r0;
+                ring[0][1][lane + 1] = r1;
+            }
+            if (hcol >= 0) {
+                double r0 = rho_h[0], r1 = rho_h[1];
+                if (!mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, yb, hcol, hf);
+                    r0 = density(hf[0]);
+                    r1 = density(hf[1]);
+                }
+                ring[0][0][hent] = r0;
+                ring[0][1][hent] = r1;
+            }
+        }
+
+        // --- march up the band
+        for (int r = 0; r < nrows; ++r) {
+            const int y = y0 + r;
+            const int yn = y + 1;
+            const int sn = (r + 2) & 3;   // ring slot of row y + 1
+            const bool top_mirror = (yn == ny) && (BCY == BC_WALLS);
+            const int ynw = (yn == ny) ? 0 : yn;   // periodic image of the row above the top
+            double rn[2] = {rho_c[0], rho_c[1]};
+            if (col >= 0 && !top_mirror) {
+                pull_site<ST, BCY>(src, M, ynw, col, nxt_f);
+                rn[0] = density(nxt_f[0]);
+                rn[1] = density(nxt_f[1]);
+            }
+            if (col >= 0) {
+                ring[sn][0][lane + 1] = rn[0];
+                ring[sn][1][lane + 1] = rn[1];
+            }
+            if (hcol >= 0) {
+                if (!top_mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, ynw, hcol, hf);
+                    rho_h[0] = density(hf[0]);
+                    rho_h[1] = density(hf[1]);
+                }
+                ring[sn][0][hent] = rho_h[0];
+                ring[sn][1][hent] = rho_h[1];
+            }
+            __syncthreads();
+
+            if (active) {
+                const int sm = r & 3, s0 = (r + 1) & 3, sp = sn;
+                const int e = lane + 1;
+                // Eq. 5 neighbour sums S_sbar = sum_i w_i psi_sbar(x + c_i) c_i
+                // for both components, in index order (i = 1..8).
+                double Sx[2], Sy[2];
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const double p1 = ring[s0][o][e + 1];   // i = 1: (x+1, y)
+                    const double p2 = ring[sp][o][e];       // i = 2: (x, y+1)
+                    const double p3 = ring[s0][o][e - 1];   // i = 3: (x-1, y)
+                    const double p4 = ring[sm][o][e];       // i = 4: (x, y-1)
+                    const double p5 = ring[sp][o][e + 1];   // i = 5: (x+1, y+1)
+                    const double p6 = ring[sp][o][e - 1];   // i = 6: (x-1, y+1)
+                    const double p7 = ring[sm][o][e - 1];   // i = 7: (x-1, y-1)
+                    const double p8 = ring[sm][o][e + 1];   // i = 8: (x+1, y-1)
+                    const double w1 = wgt(1), w5 = wgt(5);
+                    double sx = w1 * p1;
+                    sx -= w1 * p3;
+                    sx += w5 * p5;
+                    sx -= w5 * p6;
+                    sx -= w5 * p7;
+                    sx += w5 * p8;
+                    double sy = w1 * p2;
+                    sy -= w1 * p4;
+                    sy += w5 * p5;
+                    sy += w5 * p6;
+                    sy -= w5 * p7;
+                    sy -= w5 * p8;
+                    Sx[o] = sx;
+                    Sy[o] = sy;
+                }
+                double jx[2], jy[2], Fx[2], Fy[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    momentum(cur_f[s], jx[s], jy[s]);
+                    // F_s = -G rho_s S_sbar + rho_s g_s   (Eq. 5 + Eq. 7)
+                    const double mg = -M.G * rho_c[s];
+                    Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
+                    Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
+                }
+                const double rt = rho_c[0] + rho_c[1];
+                if (FIELDS) {
+                    // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
+                    const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
+                    const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
+                    const int64_t k = (int64_t)y * nx + x;
+                    if (fo.rhoA) fo.rhoA[k] = rho_c[0];
+                    if (fo.rhoB) fo.rhoB[k] = rho_c[1];
+                    if (fo.ux) fo.ux[k] = ux;
+                    if (fo.uy) fo.uy[k] = uy;
+                } else {
+                    double ux, uy;
+                    if (FORCING == FORCE_SHIFT) {
+                        // Eq. 1: velocity weighted by 1/tau_s
+                        const double nxv = jx[0] / M.tau[0] + jx[1] / M.tau[1];
+                        const double nyv = jy[0] / M.tau[0] + jy[1] / M.tau[1];
+                        const double den = rho_c[0] / M.tau[0] + rho_c[1] / M.tau[1];
+                        ux = nxv / den;
+                        uy = nyv / den;
+                    } else {
+                        ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
+                        uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
+                    }
+                    const int64_t plane = M.plane;
+                    const int64_t orow = (int64_t)y * M.pitch + x;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        double vxd = ux, vyd = uy;
+                        if (FORCING == FORCE_SHIFT) {
+                            // Eq. 3: shifted velocity u + tau_s F_s / rho_s
+                            vxd = ux + M.tau[s] * Fx[s] / rho_c[s];
+                            vyd = uy + M.tau[s] * Fy[s] / rho_c[s];
+                        }
+                        const C vx = (C)vxd, vy = (C)vyd, rho = (C)rho_c[s];
+                        const C omega = (C)M.itau[s];
+                        const C vv = vx * vx + vy * vy;
+                        C gcoef = (C)0, fx = (C)0, fy = (C)0, gux = (C)0, guy = (C)0;
+                        if (FORCING == FORCE_GUO) {
+                            gcoef = (C)(1.0 - 0.5 * M.itau[s]);
+                            fx = (C)Fx[s];
+                            fy = (C)Fy[s];
+                            gux = (C)ux;
+                            guy = (C)uy;
+                        }
+                        T *d = dst + (int64_t)s * NQ * plane + orow;
+#pragma unroll
+                        for (int i = 0; i < NQ; ++i) {
+                            // c_i . v with the same operand order as sum_a c_ia v_a
+                            C cv;
+                            if (cx(i) == 0 && cy(i) == 0) cv = (C)0;
+                            else if (cy(i) == 0) cv = cx(i) > 0 ? vx : -vx;
+                            else if (cx(i) == 0) cv = cy(i) > 0 ? vy : -vy;
+                            else cv = (cx(i) > 0 ? vx : -vx) + (cy(i) > 0 ? vy : -vy);
+                            // Eq. 3
+                            const C feq = rho * (C)wgt(i) * ((C)1 + (C)3 * cv + (C)4.5 * cv * cv - (C)1.5 * vv);
+                            const C fi = cur_f[s][i];
+                            // Eq. 2
+                            C post = fi - omega * (fi - feq);
+                            if (FORCING == FORCE_GUO) {
+                                C cu;
+                                if (cx(i) == 0 && cy(i) == 0) cu = (C)0;
+                                else if (cy(i) == 0) cu = cx(i) > 0 ? gux : -gux;
+                                else if (cx(i) == 0) cu = cy(i) > 0 ? guy : -guy;
+                                else cu = (cx(i) > 0 ? gux : -gux) + (cy(i) > 0 ? guy : -guy);
+                                const C ex = (C)3 * ((C)cx(i) - gux) + (C)9 * cu * (C)cx(i);
+                                const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
+                                post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
+                            }
+                            d[(int64_t)i * plane] = Q::enc(post, M.shift[s][i], M.scale[s][i]);
+                        }
+                    }
+                }
+            }
+            // rotate: the next row becomes current
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                rho_c[s] = rn[s];
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) cur_f[s][i] = nxt_f[s][i];
+            }
+        }
+        __syncthreads();   // the ring is reused by the next item
+    }
+}
+
+// ---------------------------------------------------------------------------
+// State conversion between the canonical FP64 pre-collision populations
+// f(t)[s][i][y][x] and the stored post-collision representation.
+//
+// Scatter (inverse of the pull): stored f*_i(z) = f_i(z + c_i) when z + c_i
+// is a lattice site, else f_opp(i)(z) (the population that bounces back at z).
+// With from_rho, the canonical populations are the rest equilibrium
+// f_i = w_i rho_s (Eq. 3 with u = 0) of the given densities.
+template <int ST, int BCY>
+__global__ void k_scatter(const Member *__restrict__ members, int mi, const double *__restrict__ fcan,
+                          const double *__restrict__ rhoA, const double *__restrict__ rhoB, int from_rho, int cur)
+{
+    const Member &M = members[mi];
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    const int64_t n = (int64_t)M.nx * M.ny;
+    T *dst = (T *)M.f[cur];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / M.nx), x = (int)(k % M.nx);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            int xs = x + cx(i), ys = y + cy(i);
+            if (xs < 0) xs += M.nx;
+            if (xs >= M.nx) xs -= M.nx;
+            int isrc = i;
+            if (BCY == BC_PERIODIC) {
+                if (ys < 0) ys += M.ny;
+                if (ys >= M.ny) ys -= M.ny;
+            } else if (ys < 0 || ys >= M.ny) {
+                xs = x;
+                ys = y;
+                isrc = opp(i);
+            }
+            const int64_t ks = (int64_t)ys * M.nx + xs;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                double v;
+                if (from_rho) v = wgt(isrc) * (s == 0 ? rhoA[ks] : rhoB[ks]);
+                else v = fcan[((int64_t)s * NQ + isrc) * n + ks];
+                dst[((int64_t)s * NQ + i) * M.plane + (int64_t)y * M.pitch + x] =
+                    Q::enc((typename Q::C)v, M.shift[s][i], M.scale[s][i]);
+            }
+        }
+    }
+}
+
+// Gather: canonical f(t) = pull of the stored buffer, decoded to FP64.
+template <int ST, int BCY>
+__global__ void k_gather(const Member *__restrict__ members, int mi, double *__restrict__ fcan, int cur)
+{
+    const Member &M = members[mi];
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    const int64_t n = (int64_t)M.nx * M.ny;
+    const T *src = (const T *)M.f[cur];
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int y = (int)(k / M.nx), x = (int)(k % M.nx);
+        typename Q::C f[2][NQ];
+        pull_site<ST, BCY>(src, M, y, x, f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) fcan[((int64_t)s * NQ + i) * n + k] = (double)f[s][i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Energy-budget reductions (Sec. 3, Eq. 15-18 and Eq. 22) over the field
+// buffer [rho_A | rho_B | u_x | u_y], each [ny][nx] FP64.  Pass 1: one
+// workgroup per row writes that row's partial sums; every workgroup uses the
+// same thread count and the same combining tree, so the result does not
+// depend on the tile shape of the step.  Pass 2: one workgroup combines the
+// rows in a fixed order.
+//
+// part[row][0..8] = sum rho_A, sum rho_B, sum phi (all columns),
+//                   sum rho |u|^2 / 2, sum -y (rho_A gA_y + rho_B gB_y),
+//                   sum -u . (rho_A gA + rho_B gB), sum omega^2   (rows of D only),
+//                   max |u|, number of non-finite values.
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Combine one value per thread of a RED_THREADS block: wave shuffles, then
+// the four wave results in order.  Result valid in thread 0.
+template <bool MAX>
+__device__ __forceinline__ double block_combine(double v, double *sh)
+{
+    v = MAX ? wave_max(v) : wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int k = 1; k < RED_THREADS / 64; ++k) r = MAX ? fmax(r, sh[k]) : r + sh[k];
+    return r;
+}
+
+__global__ void __launch_bounds__(RED_THREADS)
+k_reduce_rows(const double *__restrict__ fld, int nx, int ny, int trim, double gAx, double gAy, double gBx,
+              double gBy, double *__restrict__ part)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    const int y = blockIdx.x;
+    const int64_t n = (int64_t)nx * ny;
+    const double *rA = fld, *rB = fld + n, *ux = fld + 2 * n, *uy = fld + 3 * n;
+    const bool inD = (y >= trim) && (y < ny - trim);
+    const double yj = (double)y - 0.5 * (double)(ny - 1);
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int x = threadIdx.x; x < nx; x += RED_THREADS) {
+        const int64_t k = (int64_t)y * nx + x;
+        const double ra = rA[k], rb = rB[k], vx = ux[k], vy = uy[k];
+        a[0] += ra;
+        a[1] += rb;
+        a[2] += ra - rb;
+        const double um = sqrt(vx * vx + vy * vy);
+        a[7] = fmax(a[7], um);
+        if (!(isfinite(ra) && isfinite(rb) && isfinite(vx) && isfinite(vy))) a[8] += 1.0;
+        if (inD) {
+            const double rt = ra + rb;
+            a[3] += 0.5 * rt * (vx * vx + vy * vy);
+            const double fy = ra * gAy + rb * gBy;
+            const double fx = ra * gAx + rb * gBx;
+            a[4] += -yj * fy;
+            a[5] += -(vx * fx + vy * fy);
+            const int xp = (x + 1 == nx) ? 0 : x + 1, xm = (x == 0) ? nx - 1 : x - 1;
+            const double dvy_dx = 0.5 * (uy[(int64_t)y * nx + xp] - uy[(int64_t)y * nx + xm]);
+            const double dux_dy = 0.5 * (ux[(int64_t)(y + 1) * nx + x] - ux[(int64_t)(y - 1) * nx + x]);
+            const double om = dvy_dx - dux_dy;
+            a[6] += om * om;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double r = (q == 7) ? block_combine<true>(a[q], sh) : block_combine<false>(a[q], sh);
+        if (threadIdx.x == 0) part[(int64_t)y * RED_NQ + q] = r;
+    }
+}
+
+// out[0..8] as part[] summed over rows (max for [7]); prof[y] = row mean of phi.
+__global__ void __launch_bounds__(RED_THREADS)
+k_reduce_final(const double *__restrict__ part, int nx, int ny, double *__restrict__ out, double *__restrict__ prof)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int y = threadIdx.x; y < ny; y += RED_THREADS) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const double v = part[(int64_t)y * RED_NQ + q];
+            a[q] = (q == 7) ? fmax(a[q], v) : a[q] + v;
+        }
+        if (prof) prof[y] = part[(int64_t)y * RED_NQ + 2] / (double)nx;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const double r = (q == 7) ? block_combine<true>(a[q], sh) : block_combine<false>(a[q], sh);
+        if (threadIdx.x == 0) out[q] = r;
+    }
+}
+
+}  // namespace lbk

@@ -1,0 +1,133 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/lb.h declares, and validates its arguments (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lb():
+    from paper_2101_04847_amd import lb as mod
+    return mod
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lb):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lb._lib, n), n
+    assert sorted(lb.EXPORTS) == names
+
+
+def test_header_constants_match_binding(lb):
+    src = open(os.path.join(ROOT, "include", "lb.h")).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"#define (LB_[A-Z0-9_]+) \(?(-?\d+)\)?", src))
+    assert consts["LB_OK"] == lb.LB_OK and consts["LB_EINVAL"] == lb.LB_EINVAL
+    assert consts["LB_ENOMEM"] == lb.LB_ENOMEM and consts["LB_EHIP"] == lb.LB_EHIP
+    assert consts["LB_ESTATE"] == lb.LB_ESTATE and consts["LB_ENONFINITE"] == lb.LB_ENONFINITE
+    assert (consts["LB_F64"], consts["LB_F32"], consts["LB_F16S"], consts["LB_BF16S"]) == (0, 1, 2, 3)
+    assert (consts["LB_FORCE_SHIFT"], consts["LB_FORCE_GUO"]) == (0, 1)
+    assert (consts["LB_WALLS"], consts["LB_PERIODIC_Y"]) == (0, 1)
+    assert consts["LB_MAX_MEMBERS"] == lb.MAX_MEMBERS
+    # struct sizes the binding assumes
+    assert ctypes.sizeof(lb.LbMember) == 4 * 2 + 8 * 2 + 8 + 8 * 4 + 8 * 2 + 8 * 2
+    assert ctypes.sizeof(lb.LbDiag) == 8 + 16 + 5 * 8 + 8
+
+
+def _member(lb, nx=32, ny=30, **kw):
+    r = np.ones((ny, nx))
+    return lb.Member(nx, ny, r, r, tau=kw.pop("tau", (1.0, 1.0)), **kw)
+
+
+def test_workspace_bytes_accounts_for_storage(lb):
+    m = _member(lb, 100, 40)
+    b64 = lb.workspace_bytes([m], storage=lb.F64)
+    b32 = lb.workspace_bytes([m], storage=lb.F32)
+    b16 = lb.workspace_bytes([m], storage=lb.F16S)
+    pitch = 128
+    pops = 2 * 9 * 40 * pitch
+    assert b64 - b32 == 2 * pops * 4
+    assert b32 - b16 == 2 * pops * 2
+    assert b64 >= 2 * pops * 8 + 4 * 100 * 40 * 8
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(storage=7), "storage"),
+    (dict(forcing=3), "forcing"),
+    (dict(bc_y=2), "bc_y"),
+    (dict(diag_trim=0), "diag_trim"),
+    (dict(tile_x=100), "tile_x"),
+    (dict(graph_chunk=7), "graph_chunk"),
+])
+def test_config_validation(lb, kw, msg):
+    c, _k = lb.make_config([_member(lb)], **kw)
+    assert lb._lib.lb_workspace_bytes(ctypes.byref(c)) == 0
+    assert msg in lb.last_error()
+
+
+@pytest.mark.parametrize("mkw,msg", [
+    (dict(tau=(0.5, 1.0)), "tau"),
+    (dict(tau=(1.0, float("nan"))), "tau"),
+    (dict(nx=2), "nx"),
+    (dict(ny=20), "trimming"),
+    (dict(G=float("inf")), "G_AB"),
+])
+def test_member_validation(lb, mkw, msg):
+    nx = mkw.pop("nx", 32)
+    ny = mkw.pop("ny", 30)
+    c, _k = lb.make_config([_member(lb, nx, ny, **mkw)])
+    assert lb._lib.lb_workspace_bytes(ctypes.byref(c)) == 0
+    assert msg in lb.last_error()
+
+
+def test_guo_needs_equal_tau(lb):
+    c, _k = lb.make_config([_member(lb, tau=(1.0, 0.8))], forcing=lb.FORCE_GUO)
+    assert lb._lib.lb_workspace_bytes(ctypes.byref(c)) == 0
+    assert "Guo" in lb.last_error()
+
+
+def test_init_rejects_null_and_small_workspace(lb):
+    c, _k = lb.make_config([_member(lb)])
+    h = ctypes.c_void_p()
+    assert lb._lib.lb_init(ctypes.byref(c), None, 1 << 30, None, ctypes.byref(h)) == lb.LB_EINVAL
+    assert "workspace" in lb.last_error()
+    need = lb._lib.lb_workspace_bytes(ctypes.byref(c))
+    # a fake, aligned, never dereferenced address: the size check comes first
+    assert lb._lib.lb_init(ctypes.byref(c), ctypes.c_void_p(1 << 20), need - 1, None, ctypes.byref(h)) == lb.LB_ENOMEM
+    assert lb._lib.lb_init(ctypes.byref(c), ctypes.c_void_p((1 << 20) + 8), need, None, ctypes.byref(h)) == lb.LB_EINVAL
+    assert "aligned" in lb.last_error()
+    assert lb._lib.lb_init(None, ctypes.c_void_p(1 << 20), need, None, ctypes.byref(h)) == lb.LB_EINVAL
+
+
+def test_unknown_handle_is_rejected(lb):
+    bogus = ctypes.c_void_p(0x1234)
+    assert lb._lib.lb_step(bogus, 1) == lb.LB_ESTATE
+    assert lb._lib.lb_time(bogus) == -1
+    assert lb._lib.lb_destroy(bogus) == lb.LB_ESTATE
+    assert lb._lib.lb_destroy(None) == lb.LB_ESTATE
+    d = lb.LbDiag()
+    assert lb._lib.lb_diagnostics(bogus, 0, ctypes.byref(d), None) == lb.LB_ESTATE
+    assert lb._lib.lb_fields(bogus, 0, None, None, None, None) == lb.LB_ESTATE
+    assert "live" in lb.last_error()
+
+
+def test_oracle_is_not_imported_by_the_product(lb):
+    """The product package must not reach into the test oracle."""
+    pkg = os.path.join(ROOT, "paper_2101_04847_amd")
+    for dirpath, _d, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "orc_" not in text, fn

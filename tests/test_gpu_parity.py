@@ -1,0 +1,277 @@
+"""GPU (gfx950) parity of liblb against the FP64 CPU oracle.
+
+Every case prints its name before running so that a failure names it.  The
+populations, densities and velocities of the FP64 GPU path must match the
+oracle to 1e-12 relative (max |difference| / max |oracle|); the GPU path
+evaluates the model's expressions in the same order as the oracle, so the
+match is usually exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_04847_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2101_04847_amd import lb as mod
+    return mod
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+def _pair(lb, nx, ny, *, G=1.5, g=1e-5, tau=(1.0, 1.0), forcing=0, bc=0, seed=None, amp=2.0,
+          tile=(0, 0), chunk=0, storage=None):
+    if seed is None:
+        rA, rB = inputs.single_mode(nx, ny, amp)
+    else:
+        rA, rB = inputs.multi_mode(nx, ny, seed)
+    gg = ((0.0, -g), (0.0, g))
+    m = lb.Member(nx, ny, rA, rB, tau=tau, G=G, g=gg)
+    lat = lb.Lattice([m], forcing=forcing, storage=lb.F64 if storage is None else storage, bc_y=bc,
+                     tile_x=tile[0], tile_h=tile[1], graph_chunk=chunk, poison=True,
+                     diag_trim=max(1, min(10, (ny - 1) // 2 - 1)))
+    p = oracle.Params(nx=nx, ny=ny, tau=tau, G=G, g=gg, forcing=forcing, periodic_y=bool(bc))
+    return lat, p, oracle.fill_equilibrium(p, rA, rB)
+
+
+@pytest.mark.parametrize("forcing", [1, 0], ids=["guo", "shift"])
+def test_rt_128x64_1000_steps(lb, forcing):
+    """The 128 x 64 Rayleigh-Taylor parity workload (tau = 1, G = 1.5,
+    g = 1e-5, one cosine mode) at steps 1, 10, 100 and 1000."""
+    _say("rt 128x64", "guo" if forcing else "shift")
+    lat, p, f = _pair(lb, 128, 64, forcing=forcing)
+    t = 0
+    exact = True
+    for target in (1, 10, 100, 1000):
+        f = oracle.run(p, f, target - t)
+        lat.step(target - t)
+        t = target
+        fg = lat.get_populations(0).cpu().numpy()
+        err = _rel(fg, f)
+        exact &= err == 0.0
+        assert err <= TOL, (target, err)
+        mg = {k: v.cpu().numpy() for k, v in lat.fields(0).items()}
+        mo = oracle.macro(p, f)
+        for k in ("rhoA", "rhoB", "ux", "uy"):
+            assert _rel(mg[k], mo[k]) <= TOL, (target, k)
+    assert lat.t == 1000
+    print(f"bit-exact at every checkpoint: {exact}", flush=True)
+    lat.close()
+
+
+CASES = [
+    # nx, ny, bc, forcing, tile, tau
+    (67, 13, 0, 0, (64, 5), (1.0, 1.0)),
+    (67, 13, 1, 1, (64, 4), (0.8, 0.8)),
+    (130, 23, 0, 1, (128, 7), (0.7, 0.7)),
+    (130, 23, 1, 0, (64, 32), (1.0, 0.6)),
+    (200, 37, 0, 0, (256, 16), (0.53, 0.53)),
+    (513, 21, 0, 0, (512, 8), (1.0, 1.0)),
+    (64, 40, 1, 0, (64, 40), (1.0, 1.0)),
+    (3, 3, 0, 0, (64, 1), (1.0, 1.0)),
+    (5, 7, 1, 1, (64, 2), (0.9, 0.9)),
+]
+
+
+@pytest.mark.parametrize("nx,ny,bc,forcing,tile,tau", CASES)
+def test_ragged_grids_and_tiles(lb, nx, ny, bc, forcing, tile, tau):
+    """Partial tiles in x and y, periodic-x seams inside a tile, both wall
+    modes and both forcing schemes, unequal relaxation times."""
+    _say("ragged", nx, ny, "bc", bc, "forcing", forcing, "tile", tile, "tau", tau)
+    g = 1e-4 if ny > 5 else 0.0
+    lat, p, f = _pair(lb, nx, ny, G=1.2, g=g, tau=tau, forcing=forcing, bc=bc, tile=tile,
+                      amp=min(2.0, ny / 6), chunk=-1)
+    for steps in (1, 29):
+        f = oracle.run(p, f, steps)
+        lat.step(steps)
+        assert _rel(lat.get_populations(0).cpu().numpy(), f) <= TOL
+    lat.close()
+
+
+def test_diagnostics_match_oracle(lb):
+    """Energy-budget averages (Sec. 3) of the GPU reduction against the
+    oracle's compensated serial sums: |difference| <= 1e-12 * sum |terms|."""
+    _say("diagnostics 256x120 after 300 steps")
+    nx, ny = 256, 120
+    lat, p, f = _pair(lb, nx, ny, g=1e-4, seed=7)
+    lat.step(300)
+    f = oracle.run(p, f, 300)
+    dg = lat.diagnostics(0, profile=True)
+    do = oracle.diagnostics(p, f, trim=10, profile=True)
+    m = oracle.macro(p, f)
+    D = slice(10, ny - 10)
+    rho = m["rhoA"] + m["rhoB"]
+    yj = (np.arange(ny) - 0.5 * (ny - 1))[:, None]
+    fy = m["rhoA"] * p.g[0][1] + m["rhoB"] * p.g[1][1]
+    scale = {
+        "mass_A": np.sum(np.abs(m["rhoA"])), "mass_B": np.sum(np.abs(m["rhoB"])),
+        "Ek": np.mean((0.5 * rho * (m["ux"] ** 2 + m["uy"] ** 2))[D]),
+        "Ep": np.mean(np.abs(yj * fy)[D]),
+        "buoyancy": np.mean(np.abs(m["uy"] * fy)[D]),
+        "omega2": do["omega2"], "umax": do["umax"],
+    }
+    for k, s in scale.items():
+        assert abs(dg[k] - do[k]) <= 1e-12 * s, (k, dg[k], do[k])
+    assert dg["finite"] and dg["t"] == 300
+    assert np.max(np.abs(dg["phi_profile"] - do["phi_profile"])) <= 1e-12
+    lat.close()
+
+
+def test_graph_replay_equals_eager(lb):
+    """Chunks replayed from a HIP graph give bit-identical states to eager
+    launches, from both buffer parities."""
+    _say("graph vs eager")
+    la, _, _ = _pair(lb, 160, 48, chunk=10, tile=(64, 16))
+    lb_, _, _ = _pair(lb, 160, 48, chunk=-1, tile=(64, 16))
+    for n in (3, 20, 17, 40):
+        la.step(n)
+        lb_.step(n)
+    assert la.t == lb_.t == 80
+    assert np.array_equal(la.get_populations(0).cpu().numpy(), lb_.get_populations(0).cpu().numpy())
+    la.close()
+    lb_.close()
+
+
+def test_tile_shape_does_not_change_results(lb):
+    _say("tile shapes")
+    outs = []
+    for tile in ((64, 4), (128, 16), (256, 64), (512, 3)):
+        lat, _, _ = _pair(lb, 300, 50, tile=tile, seed=3)
+        assert lat.tile_shape() == tile
+        lat.step(25)
+        outs.append(lat.get_populations(0).cpu().numpy())
+        d = lat.diagnostics(0)
+        outs.append(np.array([d["Ek"], d["Ep"], d["omega2"]]))
+        lat.close()
+    for k in range(2, len(outs)):
+        assert np.array_equal(outs[k], outs[k % 2])
+
+
+def test_ensemble_members_equal_solo_runs(lb):
+    """One launch over uneven members (sizes, couplings, forcing parameters)
+    gives each member exactly its solo result."""
+    _say("ensemble vs solo")
+    specs = [(96, 40, 0.5, 3), (160, 64, 1.5, 4), (64, 24, 1.5, 5)]
+    members = []
+    for nx, ny, G, seed in specs:
+        rA, rB = inputs.multi_mode(nx, ny, seed)
+        members.append(lb.Member(nx, ny, rA, rB, tau=(1.0, 1.0), G=G, g=((0, -1e-4), (0, 1e-4))))
+    ens = lb.Lattice(members, tile_x=64, tile_h=16, graph_chunk=4, poison=True)
+    ens.step(30)
+    for k, m in enumerate(members):
+        solo = lb.Lattice([m], tile_x=64, tile_h=16, graph_chunk=4, poison=True)
+        solo.step(30)
+        assert np.array_equal(ens.get_populations(k).cpu().numpy(), solo.get_populations(0).cpu().numpy()), k
+        solo.close()
+    ens.close()
+
+
+def test_checkpoint_resume_is_bitwise(lb):
+    _say("resume")
+    a, _, _ = _pair(lb, 128, 64, seed=11)
+    a.step(40)
+    f = a.get_populations(0)
+    b, _, _ = _pair(lb, 128, 64, seed=12)     # different initial state, replaced
+    b.set_populations(f)
+    a.step(35)
+    b.step(35)
+    assert np.array_equal(a.get_populations(0).cpu().numpy(), b.get_populations(0).cpu().numpy())
+    a.close()
+    b.close()
+
+
+def test_nonfinite_state_is_reported(lb):
+    _say("non-finite")
+    lat, _, _ = _pair(lb, 64, 30)
+    f = lat.get_populations(0)
+    f[1, 5, 12, 7] = float("nan")
+    lat.set_populations(f)
+    with pytest.raises(lb.LBError) as e:
+        lat.diagnostics(0)
+    assert e.value.code == lb.LB_ENONFINITE
+    d = lat.diagnostics(0, check_finite=False)
+    assert not d["finite"]
+    lat.close()
+
+
+def test_destroyed_handle_is_rejected(lb):
+    _say("destroy")
+    lat, _, _ = _pair(lb, 64, 30)
+    h = lat.handle
+    lat.close()
+    assert lb._lib.lb_step(h, 1) == lb.LB_ESTATE
+    assert lb._lib.lb_destroy(h) == lb.LB_ESTATE
+
+
+def _f32_round(x):
+    return np.asarray(x, np.float64).astype(np.float32)
+
+
+def _bf16_round(x32):
+    """Round float32 to bfloat16 (nearest, ties to even) with integer
+    arithmetic, returned as float32."""
+    u = np.asarray(x32, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
+def test_storage_encoding_round_trip(lb, storage):
+    """set_populations then get_populations reproduces the storage format's
+    rounding exactly: FP32 rounding, or the shifted, power-of-two-scaled
+    binary16 / bfloat16 code q = (f - w_i rho0) * scale, evaluated in FP32."""
+    import torch
+    _say("round trip", storage)
+    st = {"f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[storage]
+    lat, p, f = _pair(lb, 96, 40, storage=st, seed=5)
+    lat.set_populations(torch.from_numpy(f).cuda())
+    back = lat.get_populations(0).cpu().numpy()
+    if st == lb.F32:
+        expect = _f32_round(f).astype(np.float64)
+    else:
+        scale, shift = lat.storage_scale(0)
+        sc = scale.astype(np.float32)[:, :, None, None]
+        sh = shift.astype(np.float32)[:, :, None, None]
+        isc = (1.0 / scale).astype(np.float32)[:, :, None, None]
+        q = (_f32_round(f) - sh) * sc
+        q = q.astype(np.float16).astype(np.float32) if st == lb.F16S else _bf16_round(q)
+        expect = (sh + q * isc).astype(np.float64)
+    assert np.array_equal(back, expect)
+    lat.close()
+
+
+@pytest.mark.parametrize("storage,tol1,tol100", [("f32", 5e-7, 2e-5), ("f16s", 2e-3, 5e-2), ("bf16s", 2e-2, 3e-1)])
+def test_reduced_precision_close_to_oracle(lb, storage, tol1, tol100):
+    """Reduced-precision storage follows the FP64 oracle within bounds set by
+    the format's unit roundoff (relative density error after 1 and 100
+    steps); the errors themselves are reported by the benchmark."""
+    _say("reduced precision", storage)
+    st = {"f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[storage]
+    lat, p, f = _pair(lb, 128, 64, storage=st, g=1e-4)
+    errs = []
+    t = 0
+    for target in (1, 100):
+        f = oracle.run(p, f, target - t)
+        lat.step(target - t)
+        t = target
+        mo = oracle.macro(p, f)
+        mg = lat.fields(0)
+        errs.append(max(_rel(mg["rhoA"].cpu().numpy(), mo["rhoA"]), _rel(mg["rhoB"].cpu().numpy(), mo["rhoB"])))
+    print(storage, "density rel err after 1, 100 steps:", errs, flush=True)
+    assert errs[0] <= tol1 and errs[1] <= tol100
+    assert lat.diagnostics(0)["finite"]
+    lat.close()
