@@ -21,6 +21,7 @@
 #include "lb.h"
 #include "lb_kernels.hpp"
 
+
 using namespace lbk;
 
 namespace {
@@ -197,6 +198,8 @@ int32_t validate(const lb_config *c)
         if (mm.nx < 3 || mm.ny < 3) return fail(LB_EINVAL, "member %d: nx = %d, ny = %d must be >= 3", m, mm.nx, mm.ny);
         if ((int64_t)mm.nx * mm.ny > ((int64_t)1 << 31))
             return fail(LB_EINVAL, "member %d: %d x %d sites exceed 2^31", m, mm.nx, mm.ny);
+        if ((int64_t)2 * NQ * pitch_of(mm.nx) * (int64_t)elem_bytes(c->storage) > (int64_t)INT32_MAX)
+            return fail(LB_EINVAL, "member %d: a row block of nx = %d exceeds 2^31 bytes", m, mm.nx);
         for (int s = 0; s < 2; ++s)
             if (!(mm.tau[s] > 0.5) || !std::isfinite(mm.tau[s]))
                 return fail(LB_EINVAL, "member %d: tau[%d] = %g must be finite and > 1/2", m, s, mm.tau[s]);
@@ -474,7 +477,10 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
         M.nx = mm.nx;
         M.ny = mm.ny;
         M.pitch = (int32_t)pitch_of(mm.nx);
-        M.plane = (int64_t)mm.ny * M.pitch;
+// row blocks [y][s][i][x]: the 18 row segments of one lattice row are adjacent
+        M.istride = M.pitch;
+        M.sstride = (int64_t)NQ * M.pitch;
+        M.ystride = (int64_t)2 * NQ * M.pitch;
         M.f[0] = h->ws + L.fbuf[0][m];
         M.f[1] = h->ws + L.fbuf[1][m];
         for (int s = 0; s < 2; ++s) {

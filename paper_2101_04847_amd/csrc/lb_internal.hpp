@@ -13,9 +13,11 @@ constexpr int NQ = 9;
 // field is uniform across a workgroup and read with scalar loads.
 struct alignas(256) Member {
     int32_t nx, ny;          // lattice
-    int32_t pitch;           // elements per stored row (nx rounded up to 64)
+    int32_t pitch;           // elements per stored row segment (nx rounded up to 64)
     int32_t tiles_x, tiles_y, tile_h;
-    int64_t plane;           // ny * pitch: elements per (s, i) plane
+    int64_t sstride;         // element strides of the population buffer:
+    int64_t istride;         //   address of f_i^s(x, y) = s*sstride + i*istride
+    int64_t ystride;         //                            + y*ystride + x
     int64_t item_begin;      // first work item of this member in the step launch
     int64_t item_end;
     void *f[2];              // ping-pong population buffers, [s][i][y][pitch]

@@ -32,6 +32,17 @@
 
 #include "lb_internal.hpp"
 
+// Tuning switches (compile-time).
+#ifndef LBK_ALT_DIR
+#define LBK_ALT_DIR 1
+#endif
+#ifndef LBK_HALO_SPLIT
+#define LBK_HALO_SPLIT 1
+#endif
+#ifndef LBK_NT_STORE
+#define LBK_NT_STORE 1
+#endif
+
 namespace lbk {
 
 // ---------------------------------------------------------------------------
@@ -45,6 +56,83 @@ __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 4.0 / 9.0 : (i
 
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
+
+// ---------------------------------------------------------------------------
+// Pointers into device global memory (address space 1).  The population
+// buffers are reached through the member table, so without this the compiler
+// cannot tell them from LDS and falls back to flat accesses.
+#define LBK_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ LBK_GLOBAL T *gp(void *p) { return (LBK_GLOBAL T *)p; }
+
+// Element at a uniform base plus a per-lane 32-bit byte offset: the form the
+// hardware addresses with a scalar base register and one vector register.
+template <class T>
+__device__ __forceinline__ T ldg(const LBK_GLOBAL T *base, unsigned byte_off)
+{
+    return *(const LBK_GLOBAL T *)((const LBK_GLOBAL char *)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ LBK_GLOBAL T *at(LBK_GLOBAL T *base, unsigned byte_off)
+{
+    return (LBK_GLOBAL T *)((LBK_GLOBAL char *)base + byte_off);
+}
+
+// Buffer resources.  Populations are stored in row blocks: the 18 segments
+// f_i^s(., y) of lattice row y are adjacent, so one 128-bit resource spans a
+// whole row block; a load adds a uniform byte offset (which population) and a
+// per-lane byte offset (which column).  Accesses outside the resource read 0
+// and write nothing.
+constexpr int BUF_RAW_DWORD3 = 0x00020000;   // raw (untyped) buffer, gfx9 descriptor word 3
+constexpr int CPOL_NT = 2;                   // non-temporal cache policy bit
+
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t row_rsrc(const void *buf, int row, int64_t row_bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)buf + (int64_t)row * row_bytes), 0,
+                                             (int)row_bytes, BUF_RAW_DWORD3);
+}
+
+template <class T> __device__ __forceinline__ T bload(rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ uint16_t bload<uint16_t>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+}
+
+template <int AUX>
+__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void bstore(_Float16 v, rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ void bstore(uint16_t v, rsrc_t r, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, AUX);
+}
 
 // ---------------------------------------------------------------------------
 // Storage traits: element type T in memory, arithmetic type C of the collision.
@@ -95,15 +183,20 @@ template <> struct Tr<ST_BF16S> {
 // post-collision buffer src (streaming with periodic x, and either halfway
 // bounce-back walls or periodic y).
 template <int ST, int BCY>
-__device__ __forceinline__ void pull_site(const typename Tr<ST>::T *__restrict__ src, const Member &M,
-                                          int y, int c, typename Tr<ST>::C (&f)[2][NQ])
+__device__ __forceinline__ void pull_site(const void *src, const Member &M, int y, int c,
+                                          typename Tr<ST>::C (&f)[2][NQ])
 {
     using Q = Tr<ST>;
+    using T = typename Q::T;
     const int nx = M.nx, ny = M.ny;
-    const int64_t plane = M.plane, pitch = M.pitch;
-    const int cm = (c == 0) ? nx - 1 : c - 1;  // source column for c_x = +1
-    const int cp = (c == nx - 1) ? 0 : c + 1;  // source column for c_x = -1
-    int ym = y - 1, yp = y + 1;                 // source rows for c_y = +1 / -1
+    const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
+    const unsigned is = (unsigned)M.istride * (unsigned)sizeof(T);   // bytes between populations
+    const unsigned ss = (unsigned)M.sstride * (unsigned)sizeof(T);   // bytes between components
+    // per-lane byte offsets of the three source columns
+    const unsigned oc = (unsigned)c * (unsigned)sizeof(T);
+    const unsigned om = (unsigned)((c == 0) ? nx - 1 : c - 1) * (unsigned)sizeof(T);  // c_x = +1
+    const unsigned op = (unsigned)((c == nx - 1) ? 0 : c + 1) * (unsigned)sizeof(T);  // c_x = -1
+    int ym = y - 1, yp = y + 1;                                   // source rows for c_y = +1 / -1
     bool bb_lo = false, bb_hi = false;
     if (BCY == BC_PERIODIC) {
         if (ym < 0) ym = ny - 1;
@@ -111,32 +204,34 @@ __device__ __forceinline__ void pull_site(const typename Tr<ST>::T *__restrict__
     } else {
         bb_lo = ym < 0;
         bb_hi = yp >= ny;
+        if (bb_lo) ym = y;   // not read
+        if (bb_hi) yp = y;
     }
-    const int64_t r0 = (int64_t)y * pitch;
-    const int64_t rm = (int64_t)ym * pitch;
-    const int64_t rp = (int64_t)yp * pitch;
+    const rsrc_t r0 = row_rsrc(src, y, row_bytes);
+    const rsrc_t rm = row_rsrc(src, ym, row_bytes);
+    const rsrc_t rp = row_rsrc(src, yp, row_bytes);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const typename Q::T *b = src + (int64_t)s * NQ * plane;
-        // offsets of the nine sources (bounce-back: same site, reversed velocity)
-        const int64_t o0 = 0 * plane + r0 + c;
-        const int64_t o1 = 1 * plane + r0 + cm;
-        const int64_t o3 = 3 * plane + r0 + cp;
-        const int64_t o2 = bb_lo ? 4 * plane + r0 + c : 2 * plane + rm + c;
-        const int64_t o5 = bb_lo ? 7 * plane + r0 + c : 5 * plane + rm + cm;
-        const int64_t o6 = bb_lo ? 8 * plane + r0 + c : 6 * plane + rm + cp;
-        const int64_t o4 = bb_hi ? 2 * plane + r0 + c : 4 * plane + rp + c;
-        const int64_t o7 = bb_hi ? 5 * plane + r0 + c : 7 * plane + rp + cp;
-        const int64_t o8 = bb_hi ? 6 * plane + r0 + c : 8 * plane + rp + cm;
-        f[s][0] = Q::dec(b[o0], M.shift[s][0], M.iscale[s][0]);
-        f[s][1] = Q::dec(b[o1], M.shift[s][1], M.iscale[s][1]);
-        f[s][2] = Q::dec(b[o2], M.shift[s][2], M.iscale[s][2]);
-        f[s][3] = Q::dec(b[o3], M.shift[s][3], M.iscale[s][3]);
-        f[s][4] = Q::dec(b[o4], M.shift[s][4], M.iscale[s][4]);
-        f[s][5] = Q::dec(b[o5], M.shift[s][5], M.iscale[s][5]);
-        f[s][6] = Q::dec(b[o6], M.shift[s][6], M.iscale[s][6]);
-        f[s][7] = Q::dec(b[o7], M.shift[s][7], M.iscale[s][7]);
-        f[s][8] = Q::dec(b[o8], M.shift[s][8], M.iscale[s][8]);
+        const unsigned b = (unsigned)s * ss;
+        // the nine sources (bounce-back: same site, reversed velocity)
+        const T v0 = bload<T>(r0, oc, b + 0 * is);
+        const T v1 = bload<T>(r0, om, b + 1 * is);
+        const T v3 = bload<T>(r0, op, b + 3 * is);
+        const T v2 = bb_lo ? bload<T>(r0, oc, b + 4 * is) : bload<T>(rm, oc, b + 2 * is);
+        const T v5 = bb_lo ? bload<T>(r0, oc, b + 7 * is) : bload<T>(rm, om, b + 5 * is);
+        const T v6 = bb_lo ? bload<T>(r0, oc, b + 8 * is) : bload<T>(rm, op, b + 6 * is);
+        const T v4 = bb_hi ? bload<T>(r0, oc, b + 2 * is) : bload<T>(rp, oc, b + 4 * is);
+        const T v7 = bb_hi ? bload<T>(r0, oc, b + 5 * is) : bload<T>(rp, op, b + 7 * is);
+        const T v8 = bb_hi ? bload<T>(r0, oc, b + 6 * is) : bload<T>(rp, om, b + 8 * is);
+        f[s][0] = Q::dec(v0, M.shift[s][0], M.iscale[s][0]);
+        f[s][1] = Q::dec(v1, M.shift[s][1], M.iscale[s][1]);
+        f[s][2] = Q::dec(v2, M.shift[s][2], M.iscale[s][2]);
+        f[s][3] = Q::dec(v3, M.shift[s][3], M.iscale[s][3]);
+        f[s][4] = Q::dec(v4, M.shift[s][4], M.iscale[s][4]);
+        f[s][5] = Q::dec(v5, M.shift[s][5], M.iscale[s][5]);
+        f[s][6] = Q::dec(v6, M.shift[s][6], M.iscale[s][6]);
+        f[s][7] = Q::dec(v7, M.shift[s][7], M.iscale[s][7]);
+        f[s][8] = Q::dec(v8, M.shift[s][8], M.iscale[s][8]);
     }
 }
 
@@ -196,27 +291,43 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         const int x0 = tx * TX;
         const int y0 = ty * M.tile_h;
         const int nrows = min(M.tile_h, ny - y0);
-        const T *__restrict__ src = (const T *)M.f[cur];
-        T *__restrict__ dst = (T *)M.f[cur ^ 1];
+        const void *src = M.f[cur];
+        void *dst = M.f[cur ^ 1];
+#if LBK_ALT_DIR
+        // odd bands march down, so that two vertically adjacent bands read
+        // the rows they share at the same time (both at their start or both
+        // at their end): the second read then hits the cache
+        const int dir = (ty & 1) ? -1 : 1;
+#else
+        const int dir = 1;
+#endif
+        const int yfirst = dir > 0 ? y0 : y0 + nrows - 1;
 
         const int x = x0 + lane;
         const bool active = x < nx;
         // column pulled by this lane: its own, or column 0 (periodic image)
         // for the first lane past the right edge of the lattice
         const int col = active ? x : (x == nx ? 0 : -1);
-        // halo columns of the ring: lane 0 pulls x0 - 1, lane 1 pulls x0 + TX
+        // halo columns of the ring: x0 - 1 and x0 + TX (the latter only when
+        // the tile's last column is inside the lattice)
+#if LBK_HALO_SPLIT
+        constexpr int HL = 0, HR = TX - 1;      // first lane of the first wave, last lane of the last wave
+#else
+        constexpr int HL = 0, HR = 1;
+#endif
         int hcol = -1;
-        if (lane == 0) hcol = (x0 == 0) ? nx - 1 : x0 - 1;
-        if (lane == 1 && x0 + TX <= nx) hcol = (x0 + TX == nx) ? 0 : x0 + TX;
-        const int hent = (lane == 0) ? 0 : LW - 1;
+        if (lane == HL) hcol = (x0 == 0) ? nx - 1 : x0 - 1;
+        if (lane == HR && x0 + TX <= nx) hcol = (x0 + TX == nx) ? 0 : x0 + TX;
+        const int hent = (lane == HL) ? 0 : LW - 1;
 
         C cur_f[2][NQ], nxt_f[2][NQ];
         double rho_c[2] = {0.0, 0.0};   // rho of this lane's column at the current row
         double rho_h[2] = {0.0, 0.0};   // rho of the halo column at the last row fetched
 
-        // --- prologue: row y0 (full) and row y0 - 1 (densities only)
+        // --- prologue: the first row of the march (full) and the row behind
+        // it (densities only).  Ring slot of march index k is (k + 1) & 3.
         if (col >= 0) {
-            pull_site<ST, BCY>(src, M, y0, col, cur_f);
+            pull_site<ST, BCY>(src, M, yfirst, col, cur_f);
             rho_c[0] = density(cur_f[0]);
             rho_c[1] = density(cur_f[1]);
             ring[1][0][lane + 1] = rho_c[0];
@@ -224,17 +335,20 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         }
         if (hcol >= 0) {
             C hf[2][NQ];
-            pull_site<ST, BCY>(src, M, y0, hcol, hf);
+            pull_site<ST, BCY>(src, M, yfirst, hcol, hf);
             rho_h[0] = density(hf[0]);
             rho_h[1] = density(hf[1]);
             ring[1][0][hent] = rho_h[0];
             ring[1][1][hent] = rho_h[1];
         }
         {
-            // row below the band: a real row, the periodic image of the top
-            // row, or (walls) the mirror of row 0
-            const bool mirror = (y0 == 0) && (BCY == BC_WALLS);
-            const int yb = (y0 == 0) ? ny - 1 : y0 - 1;
+            // the row behind: a real row, a periodic image, or (walls) the
+            // mirror of the first row
+            int yb = yfirst - dir;
+            const bool outside = (yb < 0) || (yb >= ny);
+            const bool mirror = outside && (BCY == BC_WALLS);
+            if (yb < 0) yb += ny;
+            if (yb >= ny) yb -= ny;
             if (col >= 0) {
                 double r0 = rho_c[0], r1 = rho_c[1];
                 if (!mirror) {
@@ -259,16 +373,18 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             }
         }
 
-        // --- march up the band
+        // --- march through the band
         for (int r = 0; r < nrows; ++r) {
-            const int y = y0 + r;
-            const int yn = y + 1;
-            const int sn = (r + 2) & 3;   // ring slot of row y + 1
-            const bool top_mirror = (yn == ny) && (BCY == BC_WALLS);
-            const int ynw = (yn == ny) ? 0 : yn;   // periodic image of the row above the top
+            const int y = yfirst + dir * r;
+            int yn = y + dir;                   // the row ahead
+            const int sn = (r + 2) & 3;         // its ring slot
+            const bool outside = (yn < 0) || (yn >= ny);
+            const bool mirror = outside && (BCY == BC_WALLS);
+            if (yn < 0) yn += ny;
+            if (yn >= ny) yn -= ny;
             double rn[2] = {rho_c[0], rho_c[1]};
-            if (col >= 0 && !top_mirror) {
-                pull_site<ST, BCY>(src, M, ynw, col, nxt_f);
+            if (col >= 0 && !mirror) {
+                pull_site<ST, BCY>(src, M, yn, col, nxt_f);
                 rn[0] = density(nxt_f[0]);
                 rn[1] = density(nxt_f[1]);
             }
@@ -277,9 +393,9 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 ring[sn][1][lane + 1] = rn[1];
             }
             if (hcol >= 0) {
-                if (!top_mirror) {
+                if (!mirror) {
                     C hf[2][NQ];
-                    pull_site<ST, BCY>(src, M, ynw, hcol, hf);
+                    pull_site<ST, BCY>(src, M, yn, hcol, hf);
                     rho_h[0] = density(hf[0]);
                     rho_h[1] = density(hf[1]);
                 }
@@ -289,7 +405,10 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             __syncthreads();
 
             if (active) {
-                const int sm = r & 3, s0 = (r + 1) & 3, sp = sn;
+                // ring slots of rows y - 1, y, y + 1
+                const int s0 = (r + 1) & 3;
+                const int sp = dir > 0 ? sn : (r & 3);
+                const int sm = dir > 0 ? (r & 3) : sn;
                 const int e = lane + 1;
                 // Eq. 5 neighbour sums S_sbar = sum_i w_i psi_sbar(x + c_i) c_i
                 // for both components, in index order (i = 1..8).
@@ -352,8 +471,10 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                         ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
                         uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
                     }
-                    const int64_t plane = M.plane;
-                    const int64_t orow = (int64_t)y * M.pitch + x;
+                    const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
+                    const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+                    const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+                    const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         double vxd = ux, vyd = uy;
@@ -373,7 +494,6 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                             gux = (C)ux;
                             guy = (C)uy;
                         }
-                        T *d = dst + (int64_t)s * NQ * plane + orow;
 #pragma unroll
                         for (int i = 0; i < NQ; ++i) {
                             // c_i . v with the same operand order as sum_a c_ia v_a
@@ -397,12 +517,13 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                                 const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
                                 post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
                             }
-                            d[(int64_t)i * plane] = Q::enc(post, M.shift[s][i], M.scale[s][i]);
+                            const T v = Q::enc(post, M.shift[s][i], M.scale[s][i]);
+                            bstore<LBK_NT_STORE ? CPOL_NT : 0>(v, wr, ox, (unsigned)s * wss + (unsigned)i * wis);
                         }
                     }
                 }
             }
-            // rotate: the next row becomes current
+            // rotate: the row ahead becomes current
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 rho_c[s] = rn[s];
@@ -430,7 +551,7 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
     using Q = Tr<ST>;
     using T = typename Q::T;
     const int64_t n = (int64_t)M.nx * M.ny;
-    T *dst = (T *)M.f[cur];
+    LBK_GLOBAL T *dst = gp<T>(M.f[cur]);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / M.nx), x = (int)(k % M.nx);
 #pragma unroll
@@ -453,7 +574,7 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
                 double v;
                 if (from_rho) v = wgt(isrc) * (s == 0 ? rhoA[ks] : rhoB[ks]);
                 else v = fcan[((int64_t)s * NQ + isrc) * n + ks];
-                dst[((int64_t)s * NQ + i) * M.plane + (int64_t)y * M.pitch + x] =
+                dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] =
                     Q::enc((typename Q::C)v, M.shift[s][i], M.scale[s][i]);
             }
         }
@@ -468,7 +589,7 @@ __global__ void k_gather(const Member *__restrict__ members, int mi, double *__r
     using Q = Tr<ST>;
     using T = typename Q::T;
     const int64_t n = (int64_t)M.nx * M.ny;
-    const T *src = (const T *)M.f[cur];
+    const void *src = M.f[cur];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / M.nx), x = (int)(k % M.nx);
         typename Q::C f[2][NQ];
