@@ -257,8 +257,11 @@ void plan_tiles(lb_handle *h, int tx, int th)
         M.tiles_x = (M.nx + tx - 1) / tx;
         M.tile_h = std::min(th, M.ny);
         M.tiles_y = (M.ny + M.tile_h - 1) / M.tile_h;
+        const int64_t tiles = (int64_t)M.tiles_x * M.tiles_y;
+        M.tiles_per_xcd = (int32_t)((tiles + N_XCD - 1) / N_XCD);
+        // items of a member start at a multiple of N_XCD (see k_step)
         M.item_begin = item;
-        item += (int64_t)M.tiles_x * M.tiles_y;
+        item += (int64_t)M.tiles_per_xcd * N_XCD;
         M.item_end = item;
     }
     h->n_items = item;

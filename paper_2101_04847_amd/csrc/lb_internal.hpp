@@ -8,6 +8,7 @@
 namespace lbk {
 
 constexpr int NQ = 9;
+constexpr int N_XCD = 8;     // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // One ensemble member as the kernels see it.  Lives in the workspace; every
 // field is uniform across a workgroup and read with scalar loads.
@@ -15,6 +16,7 @@ struct alignas(256) Member {
     int32_t nx, ny;          // lattice
     int32_t pitch;           // elements per stored row segment (nx rounded up to 64)
     int32_t tiles_x, tiles_y, tile_h;
+    int32_t tiles_per_xcd;   // tiles of this member handled by each of the 8 XCDs
     int64_t sstride;         // element strides of the population buffer:
     int64_t istride;         //   address of f_i^s(x, y) = s*sstride + i*istride
     int64_t ystride;         //                            + y*ystride + x

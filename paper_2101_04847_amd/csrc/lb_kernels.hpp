@@ -39,6 +39,12 @@
 #ifndef LBK_HALO_SPLIT
 #define LBK_HALO_SPLIT 1
 #endif
+#ifndef LBK_XCD_MAP
+#define LBK_XCD_MAP 0
+#endif
+#ifndef LBK_PIPE
+#define LBK_PIPE 1
+#endif
 #ifndef LBK_NT_STORE
 #define LBK_NT_STORE 1
 #endif
@@ -204,7 +210,7 @@ __device__ __forceinline__ void pull_site(const void *src, const Member &M, int 
     } else {
         bb_lo = ym < 0;
         bb_hi = yp >= ny;
-        if (bb_lo) ym = y;   // not read
+        if (bb_lo) ym = y;   // bounce-back sources lie in row y
         if (bb_hi) yp = y;
     }
     const rsrc_t r0 = row_rsrc(src, y, row_bytes);
@@ -213,16 +219,18 @@ __device__ __forceinline__ void pull_site(const void *src, const Member &M, int 
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         const unsigned b = (unsigned)s * ss;
-        // the nine sources (bounce-back: same site, reversed velocity)
+        // the nine sources; beyond a wall (bounce-back) the population comes
+        // from the same site with the reversed velocity, and rm / rp then
+        // address row y itself
         const T v0 = bload<T>(r0, oc, b + 0 * is);
         const T v1 = bload<T>(r0, om, b + 1 * is);
         const T v3 = bload<T>(r0, op, b + 3 * is);
-        const T v2 = bb_lo ? bload<T>(r0, oc, b + 4 * is) : bload<T>(rm, oc, b + 2 * is);
-        const T v5 = bb_lo ? bload<T>(r0, oc, b + 7 * is) : bload<T>(rm, om, b + 5 * is);
-        const T v6 = bb_lo ? bload<T>(r0, oc, b + 8 * is) : bload<T>(rm, op, b + 6 * is);
-        const T v4 = bb_hi ? bload<T>(r0, oc, b + 2 * is) : bload<T>(rp, oc, b + 4 * is);
-        const T v7 = bb_hi ? bload<T>(r0, oc, b + 5 * is) : bload<T>(rp, op, b + 7 * is);
-        const T v8 = bb_hi ? bload<T>(r0, oc, b + 6 * is) : bload<T>(rp, om, b + 8 * is);
+        const T v2 = bload<T>(rm, oc, b + (bb_lo ? 4 : 2) * is);
+        const T v5 = bload<T>(rm, bb_lo ? oc : om, b + (bb_lo ? 7 : 5) * is);
+        const T v6 = bload<T>(rm, bb_lo ? oc : op, b + (bb_lo ? 8 : 6) * is);
+        const T v4 = bload<T>(rp, oc, b + (bb_hi ? 2 : 4) * is);
+        const T v7 = bload<T>(rp, bb_hi ? oc : op, b + (bb_hi ? 5 : 7) * is);
+        const T v8 = bload<T>(rp, bb_hi ? oc : om, b + (bb_hi ? 6 : 8) * is);
         f[s][0] = Q::dec(v0, M.shift[s][0], M.iscale[s][0]);
         f[s][1] = Q::dec(v1, M.shift[s][1], M.iscale[s][1]);
         f[s][2] = Q::dec(v2, M.shift[s][2], M.iscale[s][2]);
@@ -268,6 +276,133 @@ __device__ __forceinline__ void momentum(const C (&f)[NQ], double &jx, double &j
 // buffer.  FIELDS = true: write rho_A, rho_B and the hydrodynamic velocity of
 // f(t) instead (no state change).  Work items are tiles of TX columns by
 // tile_h rows, numbered per member; a launch covers items [item0, item0 + n).
+// Force, collision and store (or field output) of one row for one lane:
+// Eq. 5 and 7 from the density ring, then Eq. 1-3 and the BGK relaxation of
+// Eq. 2 (or Guo forcing).  s0, sp, sm are the ring slots of rows y, y + 1 and
+// y - 1; e is this lane's ring column.
+template <int ST, int FORCING, bool FIELDS, int LW>
+__device__ __forceinline__ void row_update(const Member &M, const double (&ring)[4][2][LW], int s0, int sp, int sm,
+                                           int e, int x, int y, const typename Tr<ST>::C (&cur_f)[2][NQ],
+                                           const double (&rho_c)[2], void *dst, const FieldOut &fo)
+{
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    using C = typename Q::C;
+    const int nx = M.nx;
+    // Eq. 5 neighbour sums S_sbar = sum_i w_i psi_sbar(x + c_i) c_i
+    // for both components, in index order (i = 1..8).
+    double Sx[2], Sy[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        const double p1 = ring[s0][o][e + 1];   // i = 1: (x+1, y)
+        const double p2 = ring[sp][o][e];       // i = 2: (x, y+1)
+        const double p3 = ring[s0][o][e - 1];   // i = 3: (x-1, y)
+        const double p4 = ring[sm][o][e];       // i = 4: (x, y-1)
+        const double p5 = ring[sp][o][e + 1];   // i = 5: (x+1, y+1)
+        const double p6 = ring[sp][o][e - 1];   // i = 6: (x-1, y+1)
+        const double p7 = ring[sm][o][e - 1];   // i = 7: (x-1, y-1)
+        const double p8 = ring[sm][o][e + 1];   // i = 8: (x+1, y-1)
+        const double w1 = wgt(1), w5 = wgt(5);
+        double sx = w1 * p1;
+        sx -= w1 * p3;
+        sx += w5 * p5;
+        sx -= w5 * p6;
+        sx -= w5 * p7;
+        sx += w5 * p8;
+        double sy = w1 * p2;
+        sy -= w1 * p4;
+        sy += w5 * p5;
+        sy += w5 * p6;
+        sy -= w5 * p7;
+        sy -= w5 * p8;
+        Sx[o] = sx;
+        Sy[o] = sy;
+    }
+    double jx[2], jy[2], Fx[2], Fy[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        momentum(cur_f[s], jx[s], jy[s]);
+        // F_s = -G rho_s S_sbar + rho_s g_s   (Eq. 5 + Eq. 7)
+        const double mg = -M.G * rho_c[s];
+        Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
+        Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
+    }
+    const double rt = rho_c[0] + rho_c[1];
+    if (FIELDS) {
+        // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
+        const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
+        const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
+        const int64_t k = (int64_t)y * nx + x;
+        if (fo.rhoA) fo.rhoA[k] = rho_c[0];
+        if (fo.rhoB) fo.rhoB[k] = rho_c[1];
+        if (fo.ux) fo.ux[k] = ux;
+        if (fo.uy) fo.uy[k] = uy;
+    } else {
+        double ux, uy;
+        if (FORCING == FORCE_SHIFT) {
+            // Eq. 1: velocity weighted by 1/tau_s
+            const double nxv = jx[0] / M.tau[0] + jx[1] / M.tau[1];
+            const double nyv = jy[0] / M.tau[0] + jy[1] / M.tau[1];
+            const double den = rho_c[0] / M.tau[0] + rho_c[1] / M.tau[1];
+            ux = nxv / den;
+            uy = nyv / den;
+        } else {
+            ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
+            uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
+        }
+        const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
+        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+        const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+        const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            double vxd = ux, vyd = uy;
+            if (FORCING == FORCE_SHIFT) {
+                // Eq. 3: shifted velocity u + tau_s F_s / rho_s
+                vxd = ux + M.tau[s] * Fx[s] / rho_c[s];
+                vyd = uy + M.tau[s] * Fy[s] / rho_c[s];
+            }
+            const C vx = (C)vxd, vy = (C)vyd, rho = (C)rho_c[s];
+            const C omega = (C)M.itau[s];
+            const C vv = vx * vx + vy * vy;
+            C gcoef = (C)0, fx = (C)0, fy = (C)0, gux = (C)0, guy = (C)0;
+            if (FORCING == FORCE_GUO) {
+                gcoef = (C)(1.0 - 0.5 * M.itau[s]);
+                fx = (C)Fx[s];
+                fy = (C)Fy[s];
+                gux = (C)ux;
+                guy = (C)uy;
+            }
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) {
+                // c_i . v with the same operand order as sum_a c_ia v_a
+                C cv;
+                if (cx(i) == 0 && cy(i) == 0) cv = (C)0;
+                else if (cy(i) == 0) cv = cx(i) > 0 ? vx : -vx;
+                else if (cx(i) == 0) cv = cy(i) > 0 ? vy : -vy;
+                else cv = (cx(i) > 0 ? vx : -vx) + (cy(i) > 0 ? vy : -vy);
+                // Eq. 3
+                const C feq = rho * (C)wgt(i) * ((C)1 + (C)3 * cv + (C)4.5 * cv * cv - (C)1.5 * vv);
+                const C fi = cur_f[s][i];
+                // Eq. 2
+                C post = fi - omega * (fi - feq);
+                if (FORCING == FORCE_GUO) {
+                    C cu;
+                    if (cx(i) == 0 && cy(i) == 0) cu = (C)0;
+                    else if (cy(i) == 0) cu = cx(i) > 0 ? gux : -gux;
+                    else if (cx(i) == 0) cu = cy(i) > 0 ? guy : -guy;
+                    else cu = (cx(i) > 0 ? gux : -gux) + (cy(i) > 0 ? guy : -guy);
+                    const C ex = (C)3 * ((C)cx(i) - gux) + (C)9 * cu * (C)cx(i);
+                    const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
+                    post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
+                }
+                const T v = Q::enc(post, M.shift[s][i], M.scale[s][i]);
+                bstore<LBK_NT_STORE ? CPOL_NT : 0>(v, wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+            }
+        }
+    }
+}
+
 template <int ST, int FORCING, int BCY, int TX, bool FIELDS>
 __global__ void __launch_bounds__(TX)
 k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur,
@@ -285,9 +420,20 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         while (m + 1 < n_members && members[m].item_end <= item) ++m;
         const Member &M = members[m];
         const int nx = M.nx, ny = M.ny;
+        // Work item -> tile.  Workgroup b runs on XCD b mod 8, each XCD with
+        // its own L2; the member's items start at a multiple of 8, so XCD k
+        // receives tiles [k Q, (k + 1) Q) of the row-major tile order: a
+        // horizontal band of the lattice whose neighbouring tiles share halo
+        // rows and columns through that L2.
         const int64_t local = item - M.item_begin;
-        const int tx = (int)(local % M.tiles_x);
-        const int ty = (int)(local / M.tiles_x);
+#if LBK_XCD_MAP
+        const int64_t t = (int64_t)(local % N_XCD) * M.tiles_per_xcd + local / N_XCD;
+#else
+        const int64_t t = local;
+#endif
+        if (t >= (int64_t)M.tiles_x * M.tiles_y) continue;   // padding item (uniform)
+        const int tx = (int)(t % M.tiles_x);
+        const int ty = (int)(t / M.tiles_x);
         const int x0 = tx * TX;
         const int y0 = ty * M.tile_h;
         const int nrows = min(M.tile_h, ny - y0);
@@ -320,6 +466,134 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         if (lane == HR && x0 + TX <= nx) hcol = (x0 + TX == nx) ? 0 : x0 + TX;
         const int hent = (lane == HL) ? 0 : LW - 1;
 
+#if LBK_PIPE
+        // Software-pipelined march: the populations of the row two ahead are
+        // requested before the barrier and the collision of the current row,
+        // so one row of loads is always in flight behind the arithmetic.  The
+        // loop is unrolled three times with rotating register sets so that no
+        // register holding an outstanding load is ever copied.
+        // Every lane issues every load (idle lanes read column 0), so that
+        // the only branches around loads are uniform ones.
+        const int lcol = col >= 0 ? col : 0;
+        C fa[2][NQ], fb[2][NQ], fc[2][NQ];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) fa[s][i] = fb[s][i] = fc[s][i] = (C)0;
+        double rho_c[2] = {0.0, 0.0};   // rho of this lane's column at the current row
+        double rho_h[2] = {0.0, 0.0};   // rho of the halo column at the last row fetched
+
+        // --- prologue: the first row of the march (full) and the row behind
+        // it (densities only).  Ring slot of march index k is (k + 1) & 3.
+        pull_site<ST, BCY>(src, M, yfirst, lcol, fa);
+        rho_c[0] = density(fa[0]);
+        rho_c[1] = density(fa[1]);
+        ring[1][0][lane + 1] = rho_c[0];
+        ring[1][1][lane + 1] = rho_c[1];
+        if (hcol >= 0) {
+            C hf[2][NQ];
+            pull_site<ST, BCY>(src, M, yfirst, hcol, hf);
+            rho_h[0] = density(hf[0]);
+            rho_h[1] = density(hf[1]);
+            ring[1][0][hent] = rho_h[0];
+            ring[1][1][hent] = rho_h[1];
+        }
+        {
+            int yb = yfirst - dir;
+            const bool mirror = ((yb < 0) || (yb >= ny)) && (BCY == BC_WALLS);
+            if (yb < 0) yb += ny;
+            if (yb >= ny) yb -= ny;
+            {
+                double r0 = rho_c[0], r1 = rho_c[1];
+                if (!mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, yb, lcol, hf);
+                    r0 = density(hf[0]);
+                    r1 = density(hf[1]);
+                }
+                ring[0][0][lane + 1] = r0;
+                ring[0][1][lane + 1] = r1;
+            }
+            if (hcol >= 0) {
+                double r0 = rho_h[0], r1 = rho_h[1];
+                if (!mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, yb, hcol, hf);
+                    r0 = density(hf[0]);
+                    r1 = density(hf[1]);
+                }
+                ring[0][0][hent] = r0;
+                ring[0][1][hent] = r1;
+            }
+        }
+        // request the row ahead of the first one (march index 1)
+        {
+            int y1 = yfirst + dir;
+            const bool mirror = ((y1 < 0) || (y1 >= ny)) && (BCY == BC_WALLS);
+            if (y1 < 0) y1 += ny;
+            if (y1 >= ny) y1 -= ny;
+            if (!mirror) pull_site<ST, BCY>(src, M, y1, lcol, fb);
+        }
+
+        // one march step: cf holds row r, nf the (requested) row r + 1; the
+        // row r + 2 is requested into pf
+        auto step = [&](int r, C (&cf)[2][NQ], C (&nf)[2][NQ], C (&pf)[2][NQ]) {
+            const int y = yfirst + dir * r;
+            int yn = y + dir;                   // the row ahead
+            const int sn = (r + 2) & 3;         // its ring slot
+            const bool mirror = ((yn < 0) || (yn >= ny)) && (BCY == BC_WALLS);
+            if (yn < 0) yn += ny;
+            if (yn >= ny) yn -= ny;
+            // evaluated on every path (mirror rows then discard it) so that
+            // nf's loads are known to have landed before nf becomes current
+            double rn[2] = {density(nf[0]), density(nf[1])};
+            if (mirror) {
+                rn[0] = rho_c[0];
+                rn[1] = rho_c[1];
+            }
+            ring[sn][0][lane + 1] = rn[0];
+            ring[sn][1][lane + 1] = rn[1];
+            if (hcol >= 0) {
+                if (!mirror) {
+                    C hf[2][NQ];
+                    pull_site<ST, BCY>(src, M, yn, hcol, hf);
+                    rho_h[0] = density(hf[0]);
+                    rho_h[1] = density(hf[1]);
+                }
+                ring[sn][0][hent] = rho_h[0];
+                ring[sn][1][hent] = rho_h[1];
+            }
+            if (r + 2 <= nrows) {
+                // the row after next: inside the band, or the halo row beyond it
+                int y2 = y + 2 * dir;
+                const bool mirror2 = ((y2 < 0) || (y2 >= ny)) && (BCY == BC_WALLS);
+                if (y2 < 0) y2 += ny;
+                if (y2 >= ny) y2 -= ny;
+                if (!mirror2) pull_site<ST, BCY>(src, M, y2, lcol, pf);
+            }
+            __syncthreads();
+            if (active) {
+                const int s0 = (r + 1) & 3;
+                const int sp = dir > 0 ? sn : (r & 3);
+                const int sm = dir > 0 ? (r & 3) : sn;
+                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, cf, rho_c, dst, fo);
+            }
+            rho_c[0] = rn[0];
+            rho_c[1] = rn[1];
+        };
+        // whole triples without branches inside (keeps the compiler's
+        // tracking of outstanding loads exact), then the remainder
+        int r = 0;
+        for (; r + 3 <= nrows; r += 3) {
+            step(r, fa, fb, fc);
+            step(r + 1, fb, fc, fa);
+            step(r + 2, fc, fa, fb);
+        }
+        if (r < nrows) {
+            step(r, fa, fb, fc);
+            if (r + 1 < nrows) step(r + 1, fb, fc, fa);
+        }
+#else
         C cur_f[2][NQ], nxt_f[2][NQ];
         double rho_c[2] = {0.0, 0.0};   // rho of this lane's column at the current row
         double rho_h[2] = {0.0, 0.0};   // rho of the halo column at the last row fetched
@@ -409,119 +683,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 const int s0 = (r + 1) & 3;
                 const int sp = dir > 0 ? sn : (r & 3);
                 const int sm = dir > 0 ? (r & 3) : sn;
-                const int e = lane + 1;
-                // Eq. 5 neighbour sums S_sbar = sum_i w_i psi_sbar(x + c_i) c_i
-                // for both components, in index order (i = 1..8).
-                double Sx[2], Sy[2];
-#pragma unroll
-                for (int o = 0; o < 2; ++o) {
-                    const double p1 = ring[s0][o][e + 1];   // i = 1: (x+1, y)
-                    const double p2 = ring[sp][o][e];       // i = 2: (x, y+1)
-                    const double p3 = ring[s0][o][e - 1];   // i = 3: (x-1, y)
-                    const double p4 = ring[sm][o][e];       // i = 4: (x, y-1)
-                    const double p5 = ring[sp][o][e + 1];   // i = 5: (x+1, y+1)
-                    const double p6 = ring[sp][o][e - 1];   // i = 6: (x-1, y+1)
-                    const double p7 = ring[sm][o][e - 1];   // i = 7: (x-1, y-1)
-                    const double p8 = ring[sm][o][e + 1];   // i = 8: (x+1, y-1)
-                    const double w1 = wgt(1), w5 = wgt(5);
-                    double sx = w1 * p1;
-                    sx -= w1 * p3;
-                    sx += w5 * p5;
-                    sx -= w5 * p6;
-                    sx -= w5 * p7;
-                    sx += w5 * p8;
-                    double sy = w1 * p2;
-                    sy -= w1 * p4;
-                    sy += w5 * p5;
-                    sy += w5 * p6;
-                    sy -= w5 * p7;
-                    sy -= w5 * p8;
-                    Sx[o] = sx;
-                    Sy[o] = sy;
-                }
-                double jx[2], jy[2], Fx[2], Fy[2];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    momentum(cur_f[s], jx[s], jy[s]);
-                    // F_s = -G rho_s S_sbar + rho_s g_s   (Eq. 5 + Eq. 7)
-                    const double mg = -M.G * rho_c[s];
-                    Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
-                    Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
-                }
-                const double rt = rho_c[0] + rho_c[1];
-                if (FIELDS) {
-                    // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
-                    const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
-                    const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
-                    const int64_t k = (int64_t)y * nx + x;
-                    if (fo.rhoA) fo.rhoA[k] = rho_c[0];
-                    if (fo.rhoB) fo.rhoB[k] = rho_c[1];
-                    if (fo.ux) fo.ux[k] = ux;
-                    if (fo.uy) fo.uy[k] = uy;
-                } else {
-                    double ux, uy;
-                    if (FORCING == FORCE_SHIFT) {
-                        // Eq. 1: velocity weighted by 1/tau_s
-                        const double nxv = jx[0] / M.tau[0] + jx[1] / M.tau[1];
-                        const double nyv = jy[0] / M.tau[0] + jy[1] / M.tau[1];
-                        const double den = rho_c[0] / M.tau[0] + rho_c[1] / M.tau[1];
-                        ux = nxv / den;
-                        uy = nyv / den;
-                    } else {
-                        ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
-                        uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
-                    }
-                    const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
-                    const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
-                    const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
-                    const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
-#pragma unroll
-                    for (int s = 0; s < 2; ++s) {
-                        double vxd = ux, vyd = uy;
-                        if (FORCING == FORCE_SHIFT) {
-                            // Eq. 3: shifted velocity u + tau_s F_s / rho_s
-                            vxd = ux + M.tau[s] * Fx[s] / rho_c[s];
-                            vyd = uy + M.tau[s] * Fy[s] / rho_c[s];
-                        }
-                        const C vx = (C)vxd, vy = (C)vyd, rho = (C)rho_c[s];
-                        const C omega = (C)M.itau[s];
-                        const C vv = vx * vx + vy * vy;
-                        C gcoef = (C)0, fx = (C)0, fy = (C)0, gux = (C)0, guy = (C)0;
-                        if (FORCING == FORCE_GUO) {
-                            gcoef = (C)(1.0 - 0.5 * M.itau[s]);
-                            fx = (C)Fx[s];
-                            fy = (C)Fy[s];
-                            gux = (C)ux;
-                            guy = (C)uy;
-                        }
-#pragma unroll
-                        for (int i = 0; i < NQ; ++i) {
-                            // c_i . v with the same operand order as sum_a c_ia v_a
-                            C cv;
-                            if (cx(i) == 0 && cy(i) == 0) cv = (C)0;
-                            else if (cy(i) == 0) cv = cx(i) > 0 ? vx : -vx;
-                            else if (cx(i) == 0) cv = cy(i) > 0 ? vy : -vy;
-                            else cv = (cx(i) > 0 ? vx : -vx) + (cy(i) > 0 ? vy : -vy);
-                            // Eq. 3
-                            const C feq = rho * (C)wgt(i) * ((C)1 + (C)3 * cv + (C)4.5 * cv * cv - (C)1.5 * vv);
-                            const C fi = cur_f[s][i];
-                            // Eq. 2
-                            C post = fi - omega * (fi - feq);
-                            if (FORCING == FORCE_GUO) {
-                                C cu;
-                                if (cx(i) == 0 && cy(i) == 0) cu = (C)0;
-                                else if (cy(i) == 0) cu = cx(i) > 0 ? gux : -gux;
-                                else if (cx(i) == 0) cu = cy(i) > 0 ? guy : -guy;
-                                else cu = (cx(i) > 0 ? gux : -gux) + (cy(i) > 0 ? guy : -guy);
-                                const C ex = (C)3 * ((C)cx(i) - gux) + (C)9 * cu * (C)cx(i);
-                                const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
-                                post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
-                            }
-                            const T v = Q::enc(post, M.shift[s][i], M.scale[s][i]);
-                            bstore<LBK_NT_STORE ? CPOL_NT : 0>(v, wr, ox, (unsigned)s * wss + (unsigned)i * wis);
-                        }
-                    }
-                }
+                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, cur_f, rho_c, dst, fo);
             }
             // rotate: the row ahead becomes current
 #pragma unroll
@@ -531,6 +693,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 for (int i = 0; i < NQ; ++i) cur_f[s][i] = nxt_f[s][i];
             }
         }
+#endif
         __syncthreads();   // the ring is reused by the next item
     }
 }
