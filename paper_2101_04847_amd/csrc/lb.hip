@@ -421,6 +421,7 @@ void set_scales(const lb_config *c, const lb_member &mm, Member &M)
                 M.scale[s][i] = std::ldexp(1.0f, e);
                 M.iscale[s][i] = std::ldexp(1.0f, -e);
             }
+            M.nss[s][i] = -M.shift[s][i] * M.scale[s][i];
         }
     }
 }

@@ -29,6 +29,7 @@ struct alignas(256) Member {
     float shift[2][NQ];      // 16-bit modes: w_i rho0_s; else 0
     float scale[2][NQ];      // 16-bit modes: power-of-two scale; else 1
     float iscale[2][NQ];     // 1 / scale
+    float nss[2][NQ];        // -shift * scale (exact: scale is a power of two)
 };
 
 // Storage modes (values equal the LB_F64 .. LB_BF16S constants of lb.h).

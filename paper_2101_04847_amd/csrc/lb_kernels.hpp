@@ -158,30 +158,29 @@ template <> struct Tr<ST_F32> {
     static __device__ __forceinline__ T enc(C v, float, float) { return v; }
 };
 
-// IEEE binary16 holding q = (f - shift) * scale; f = shift + q / scale.
+// IEEE binary16 holding q = (f - shift) * scale; f = shift + q / scale.  The
+// scales are powers of two, so q * (1/scale) and f * scale are exact and the
+// fused forms below round exactly like the two-operation definitions
+// (nss = -shift * scale).
 template <> struct Tr<ST_F16S> {
     using T = _Float16;
     using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return shift + (float)v * iscale; }
-    static __device__ __forceinline__ T enc(C v, float shift, float scale) { return (_Float16)((v - shift) * scale); }
+    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf((float)v, iscale, shift); }
+    static __device__ __forceinline__ T enc(C v, float nss, float scale) { return (_Float16)fmaf(v, scale, nss); }
 };
 
-// bfloat16 (kept as raw 16-bit patterns) holding the same shifted, scaled q.
+// bfloat16 (kept as raw 16-bit patterns) holding the same shifted, scaled q;
+// the conversion rounds to nearest even (gfx950 converts in hardware).
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-__device__ __forceinline__ uint16_t f32_to_bf16(float x)
-{
-    // round to nearest even on the 16 dropped mantissa bits; NaN stays NaN
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
 
 template <> struct Tr<ST_BF16S> {
     using T = uint16_t;
     using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return shift + bf16_to_f32(v) * iscale; }
-    static __device__ __forceinline__ T enc(C v, float shift, float scale) { return f32_to_bf16((v - shift) * scale); }
+    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf(bf16_to_f32(v), iscale, shift); }
+    static __device__ __forceinline__ T enc(C v, float nss, float scale)
+    {
+        return __builtin_bit_cast(uint16_t, (__bf16)fmaf(v, scale, nss));
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -328,7 +327,7 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
         Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
     }
     const double rt = rho_c[0] + rho_c[1];
-    if (FIELDS) {
+    if constexpr (FIELDS) {
         // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
         const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
         const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
@@ -337,7 +336,8 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
         if (fo.rhoB) fo.rhoB[k] = rho_c[1];
         if (fo.ux) fo.ux[k] = ux;
         if (fo.uy) fo.uy[k] = uy;
-    } else {
+    } else if constexpr (ST == ST_F64) {
+        // FP64: the definitions evaluated in their written order
         double ux, uy;
         if (FORCING == FORCE_SHIFT) {
             // Eq. 1: velocity weighted by 1/tau_s
@@ -396,9 +396,90 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
                     const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
                     post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
                 }
-                const T v = Q::enc(post, M.shift[s][i], M.scale[s][i]);
+                const T v = Q::enc(post, M.nss[s][i], M.scale[s][i]);
                 bstore<LBK_NT_STORE ? CPOL_NT : 0>(v, wr, ox, (unsigned)s * wss + (unsigned)i * wis);
             }
+        }
+    } else {
+        // Reduced-precision modes: the collision in FP32 with fused
+        // multiply-adds.  Densities and the Shan-Chen sums above stay FP64.
+        // With psi_s = rho_s the acceleration F_s / rho_s of Eq. 5 and 7 is
+        // -G S_sbar + g_s: no division.
+        const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
+        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+        const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+        const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
+        float rf[2], ax[2], ay[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            rf[s] = (float)rho_c[s];
+            ax[s] = (float)(-M.G * Sx[1 - s] + M.g[s][0]);
+            ay[s] = (float)(-M.G * Sy[1 - s] + M.g[s][1]);
+        }
+        float ux, uy;
+        if (FORCING == FORCE_SHIFT) {
+            // Eq. 1: velocity weighted by 1/tau_s
+            const float itA = (float)M.itau[0], itB = (float)M.itau[1];
+            const float iden = __builtin_amdgcn_rcpf(fmaf(rf[0], itA, rf[1] * itB));
+            ux = fmaf((float)jx[0], itA, (float)jx[1] * itB) * iden;
+            uy = fmaf((float)jy[0], itA, (float)jy[1] * itB) * iden;
+        } else {
+            // Guo: (sum_s j_s + F / 2) / rho
+            const float irt = __builtin_amdgcn_rcpf(rf[0] + rf[1]);
+            ux = fmaf(0.5f, fmaf(rf[0], ax[0], rf[1] * ax[1]), (float)jx[0] + (float)jx[1]) * irt;
+            uy = fmaf(0.5f, fmaf(rf[0], ay[0], rf[1] * ay[1]), (float)jy[0] + (float)jy[1]) * irt;
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float vx = ux, vy = uy;
+            if (FORCING == FORCE_SHIFT) {
+                // Eq. 3: shifted velocity u + tau_s a_s
+                vx = fmaf((float)M.tau[s], ax[s], ux);
+                vy = fmaf((float)M.tau[s], ay[s], uy);
+            }
+            const float r = rf[s];
+            const float om = (float)M.itau[s];
+            const float base = fmaf(-1.5f, fmaf(vx, vx, vy * vy), 1.0f);   // 1 - 3/2 v.v
+            // Guo source (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F
+            // = coef w_i [9 (c.u)(c.F) - 3 u.F] +- coef w_i 3 c.F for +-c_i
+            float coef = 0.f, fx = 0.f, fy = 0.f, uF = 0.f;
+            if (FORCING == FORCE_GUO) {
+                coef = 1.0f - 0.5f * om;
+                fx = r * ax[s];
+                fy = r * ay[s];
+                uF = fmaf(ux, fx, uy * fy);
+            }
+            const unsigned sb = (unsigned)s * wss;
+            auto put = [&](int i, float fe, float src) {
+                const float fi = cur_f[s][i];
+                float post = fmaf(om, fe - fi, fi);          // Eq. 2
+                if (FORCING == FORCE_GUO) post += src;
+                bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
+                                                    sb + (unsigned)i * wis);
+            };
+            // rest population
+            {
+                const float w = (float)wgt(0);
+                put(0, (w * r) * base, FORCING == FORCE_GUO ? coef * w * (-3.0f * uF) : 0.f);
+            }
+            // pairs (i, opp(i)) sharing |c . v|: equilibria A +- B of Eq. 3
+            auto pair = [&](int i, int o, float cu, float cvv, float cF) {
+                const float w = (float)wgt(i);
+                const float wr_ = w * r;
+                const float A = wr_ * fmaf(4.5f * cvv, cvv, base);
+                const float B = wr_ * (3.0f * cvv);
+                float Ga = 0.f, Gb = 0.f;
+                if (FORCING == FORCE_GUO) {
+                    Ga = coef * w * fmaf(9.0f * cu, cF, -3.0f * uF);
+                    Gb = coef * w * (3.0f * cF);
+                }
+                put(i, A + B, Ga + Gb);
+                put(o, A - B, Ga - Gb);
+            };
+            pair(1, 3, ux, vx, fx);                         // c = (1, 0)
+            pair(2, 4, uy, vy, fy);                         // c = (0, 1)
+            pair(5, 7, ux + uy, vx + vy, fx + fy);          // c = (1, 1)
+            pair(8, 6, ux - uy, vx - vy, fx - fy);          // c = (1, -1)
         }
     }
 }
@@ -466,7 +547,12 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         if (lane == HR && x0 + TX <= nx) hcol = (x0 + TX == nx) ? 0 : x0 + TX;
         const int hent = (lane == HL) ? 0 : LW - 1;
 
-#if LBK_PIPE
+        // The software-pipelined march keeps three rows of populations in
+        // registers; it pays off for the FP64 velocity-shift step (three waves
+        // per SIMD, two rows of loads in flight each) and is not used where
+        // the extra registers would cost occupancy.
+        constexpr bool PIPE = LBK_PIPE && ST == ST_F64 && FORCING == FORCE_SHIFT && !FIELDS;
+        if constexpr (PIPE) {
         // Software-pipelined march: the populations of the row two ahead are
         // requested before the barrier and the collision of the current row,
         // so one row of loads is always in flight behind the arithmetic.  The
@@ -593,7 +679,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             step(r, fa, fb, fc);
             if (r + 1 < nrows) step(r + 1, fb, fc, fa);
         }
-#else
+        } else {
         C cur_f[2][NQ], nxt_f[2][NQ];
         double rho_c[2] = {0.0, 0.0};   // rho of this lane's column at the current row
         double rho_h[2] = {0.0, 0.0};   // rho of the halo column at the last row fetched
@@ -693,7 +779,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 for (int i = 0; i < NQ; ++i) cur_f[s][i] = nxt_f[s][i];
             }
         }
-#endif
+        }
         __syncthreads();   // the ring is reused by the next item
     }
 }
@@ -738,7 +824,7 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
                 if (from_rho) v = wgt(isrc) * (s == 0 ? rhoA[ks] : rhoB[ks]);
                 else v = fcan[((int64_t)s * NQ + isrc) * n + ks];
                 dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] =
-                    Q::enc((typename Q::C)v, M.shift[s][i], M.scale[s][i]);
+                    Q::enc((typename Q::C)v, M.nss[s][i], M.scale[s][i]);
             }
         }
     }
