@@ -2,21 +2,23 @@
 
 One step = one pass of the whole hot path over the lattice: pull-streaming
 with periodic x and bounce-back walls, densities and Shan-Chen + buoyancy
-forces, velocity-shift BGK collision, store.  Default workload: the
+forces, velocity-shift BGK collision, store.  Headline workload: the
 10000 x 5000 Rayleigh-Taylor lattice (tau = 1, G = 1.5, g = 1e-5, 32 seeded
-interface modes), FP64 storage and arithmetic, populations resident in HBM.
+interface modes), FP64 storage and arithmetic, populations resident in HBM,
+100-step chunks replayed from HIP graphs.
 
-Prints one JSON line: million lattice updates per second (MLUPS, one update
+Prints one JSON line: million lattice updates per second (MLUPS; one update
 = both components at one site for one step), the HBM roofline of the step
-kernel, and the FP64 CPU oracle timed on a bounded sample of the same
-workload on the host's cores.
+kernel, the FP64 CPU oracle timed on a bounded sample of the same workload,
+the reduced-precision storage modes on the same lattice, and the 16-member
+batched ensemble (4 x 1024x512, 8 x 2048x1024, 4 x 4096x2048, FP32).
 
     python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s]
+    python bench.py --report out.json     # precision and ensemble studies
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,18 +32,14 @@ BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}
 METRIC = "MLUPS + % HBM peak, 2-comp D2Q9 Shan-Chen 10000×5000; ensemble MLUPS"
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for rel in ("paper_2101_04847_amd/csrc/lb_kernels.hpp", "paper_2101_04847_amd/csrc/lb.hip",
-                "paper_2101_04847_amd/csrc/lb_internal.hpp"):
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def measured_traffic(storage: str, nx: int, ny: int):
     """HBM bytes per step-kernel launch from the committed counter summary,
     if it was taken from the current kernel sources; else None."""
+    from paper_2101_04847_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"step_{storage}_{nx}x{ny}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -52,18 +50,52 @@ def measured_traffic(storage: str, nx: int, ny: int):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, rA, rB, target_s: float = 15.0) -> dict:
-    """The FP64 oracle on the host cores: full lattice, a few steps."""
-    import numpy as np
+def storage_code(lb, name):
+    return {"f64": lb.F64, "f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[name]
 
+
+def lattice_for(lb, workloads, storage, tile=(0, 0), stream=None, graph_chunk=100):
+    members = []
+    for wl in workloads:
+        rA, rB = wl.densities()
+        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity))
+    return lb.Lattice(members, forcing=lb.FORCE_SHIFT, storage=storage, tile_x=tile[0], tile_h=tile[1],
+                      graph_chunk=graph_chunk, stream=stream)
+
+
+def time_steps(lat, steps, warmup, stream):
+    """ms per step over `steps` steps, timed with events on the lattice's
+    stream after `warmup` untimed steps; plus the host wall time."""
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - w0
+
+
+def release(lat):
+    import torch
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
+def cpu_baseline(wl, target_s: float = 20.0) -> dict:
+    """The FP64 oracle on the host cores: full lattice, a few steps."""
     import oracle
     oracle.build(force=False)
+    rA, rB = wl.densities()
     p = oracle.Params(nx=wl.nx, ny=wl.ny, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
     f = oracle.fill_equilibrium(p, rA, rB)
     t0 = time.perf_counter()
     oracle.run_inplace(p, f, 1)
     one = time.perf_counter() - t0
-    n = max(1, min(20, int(target_s / max(one, 1e-6))))
+    n = max(1, min(30, int(target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
     oracle.run_inplace(p, f, n)
     dt = time.perf_counter() - t0
@@ -74,58 +106,76 @@ def cpu_baseline(wl, rA, rB, target_s: float = 15.0) -> dict:
                       f"(FP64, OpenMP over rows, {dt:.1f} s)"}
 
 
+def variant_line(lb, inputs, name, stream, steps=300, warmup=50):
+    wl = inputs.LARGE_10000x5000
+    lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream)
+    tile = lat.tile_shape()
+    ms, _ = time_steps(lat, steps, warmup, stream)
+    release(lat)
+    mlups = wl.nx * wl.ny / (ms / 1e3) / 1e6
+    return {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "tile": list(tile),
+            "bytes_per_lu": BYTES_PER_LU[name],
+            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[name] / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
+    wls = inputs.ensemble_16()
+    lat = lattice_for(lb, wls, storage_code(lb, storage), stream=stream)
+    tiles = sorted({(wl.nx, wl.ny, *lat.tile_shape(k)) for k, wl in enumerate(wls)})
+    ms, _ = time_steps(lat, steps, warmup, stream)
+    release(lat)
+    sites = sum(wl.nx * wl.ny for wl in wls)
+    mlups = sites / (ms / 1e3) / 1e6
+    return {"members": len(wls), "sites": sites, "storage": storage, "MLUPS": round(mlups, 1),
+            "ms_per_step": round(ms, 4), "graph_chunk": 100,
+            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / 1e9 / HBM_PEAK_GBS, 4),
+            "tiles": [list(t) for t in tiles],
+            "config": "4x1024x512 + 8x2048x1024 + 4x4096x2048, G alternating 0.5 / 1.5, seeds 100-115"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_LU))
-    ap.add_argument("--tile", default="", help="TXxH, e.g. 256x64 (default: timed choice)")
+    ap.add_argument("--tile", default="", help="TXxH, e.g. 256x16 (default: timed choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the storage variants and the ensemble")
+    ap.add_argument("--report", default="", help="run the precision / ensemble studies, write JSON here")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the step shards across GPUs "
-              "as described in the design notes but this build runs on a single MI355X.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the step shards across GPUs "
+              "as described in the design notes, but this build runs on a single MI355X.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_2101_04847_amd import inputs, lb
 
-    storage = {"f64": lb.F64, "f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[args.storage]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    if args.report:
+        from paper_2101_04847_amd import studies
+        rep = studies.run_all(lb, inputs, stream, log)
+        with open(args.report, "w") as fh:
+            json.dump(rep, fh, indent=1)
+        print(json.dumps({"report": args.report, "sections": sorted(rep)}), flush=True)
+        return 0
+
     wl = inputs.LARGE_10000x5000
-    rA, rB = wl.densities()
     tile = (0, 0)
     if args.tile:
         a, b = args.tile.lower().split("x")
         tile = (int(a), int(b))
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    m = lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
-    lat = lb.Lattice([m], forcing=lb.FORCE_SHIFT, storage=storage, tile_x=tile[0], tile_h=tile[1],
-                     graph_chunk=100, stream=stream)
+    lat = lattice_for(lb, [wl], storage_code(lb, args.storage), tile=tile, stream=stream)
     tx, th = lat.tile_shape()
-    print(f"[bench] {wl.name} storage={args.storage} tile={tx}x{th} warmup={args.warmup}", file=sys.stderr, flush=True)
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    lat.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    ms_step = ms / args.steps
-    sites = wl.nx * wl.ny
-    mlups = sites * args.steps / (ms / 1e3) / 1e6
+    log(f"{wl.name} storage={args.storage} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
+    ms_step, wall = time_steps(lat, args.steps, args.warmup, stream)
     d = lat.diagnostics(0)
-    lat.close()
-    del lat
-    torch.cuda.empty_cache()
+    release(lat)
+    sites = wl.nx * wl.ny
+    mlups = sites / (ms_step / 1e3) / 1e6
 
     # roofline of the step kernel: one launch per step; algorithmic bytes =
     # 2 components x 9 populations x (read + write) x element size per site
@@ -134,7 +184,8 @@ def main() -> int:
     traffic = measured_traffic(args.storage, wl.nx, wl.ny)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_lu": BYTES_PER_LU[args.storage], "kernel": "lbk::k_step"}
+            "bytes_per_lu": BYTES_PER_LU[args.storage], "kernel": "lbk::k_step",
+            "launch_ms": round(ms_step, 4)}
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -147,9 +198,17 @@ def main() -> int:
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
     }
+    if not args.no_extras:
+        out["storage_variants"] = []
+        for name in ("f32", "f16s", "bf16s"):
+            if name != args.storage:
+                log("storage variant", name)
+                out["storage_variants"].append(variant_line(lb, inputs, name, stream))
+        log("ensemble of 16")
+        out["ensemble"] = ensemble_line(lb, inputs, stream)
     if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, rA, rB)
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -93,7 +93,8 @@ typedef struct lb_member {
     const double *rhoA0;     /* host, [ny][nx]: initial densities; f(0) = w_i rho_s */
     const double *rhoB0;
     double rho0[2];          /* LB_F16S / LB_BF16S only: reference densities of the
-                                shift w_i rho0_s; 0 selects the mean initial density */
+                                shift w_i rho0_s; 0 selects the mean initial density,
+                                a negative value stores f_i unshifted */
 } lb_member;
 
 typedef struct lb_config {
@@ -171,8 +172,10 @@ int32_t lb_set_populations(lb_handle *h, int32_t m, const double *d_f);
 /* Completed steps (-1 if h is not a live handle). */
 int64_t lb_time(const lb_handle *h);
 
-/* Tile shape in use: workgroup width (columns) and rows per tile. */
-int32_t lb_tile_shape(const lb_handle *h, int32_t *tile_x, int32_t *tile_h);
+/* Tile shape of member m: workgroup width in columns (shared by all members:
+ * it is the block size of the single launch) and rows per tile (chosen per
+ * member size class when tuned). */
+int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *tile_h);
 
 /* Storage scale of member m for the 16-bit modes: scale[s*9 + i] receives
  * scale_{s,i} and shift[s*9 + i] receives w_i rho0_s (host arrays of 18;

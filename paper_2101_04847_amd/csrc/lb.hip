@@ -227,7 +227,7 @@ struct lb_handle {
     Layout L;
     int64_t t = 0;
     int cur = 0;
-    int tile_x = 0, tile_h = 0;
+    int tile_x = 0;
     int64_t n_items = 0;
     int chunk = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -248,25 +248,22 @@ bool is_live(const lb_handle *h)
 
 Member *dev_members(lb_handle *h) { return (Member *)(h->ws + h->L.members); }
 
-// Number of tiles and their assignment to work items for a given shape.
-void plan_tiles(lb_handle *h, int tx, int th)
+// Tiles of each member (tile_x columns by th[m] rows) and their work items:
+// member m owns items [item_begin, item_end) in row-major tile order.
+void plan_tiles(lb_handle *h, int tx, const std::vector<int> &th)
 {
     int64_t item = 0;
     for (size_t m = 0; m < h->dm.size(); ++m) {
         Member &M = h->dm[m];
         M.tiles_x = (M.nx + tx - 1) / tx;
-        M.tile_h = std::min(th, M.ny);
+        M.tile_h = std::max(1, std::min(th[m], M.ny));
         M.tiles_y = (M.ny + M.tile_h - 1) / M.tile_h;
-        const int64_t tiles = (int64_t)M.tiles_x * M.tiles_y;
-        M.tiles_per_xcd = (int32_t)((tiles + N_XCD - 1) / N_XCD);
-        // items of a member start at a multiple of N_XCD (see k_step)
         M.item_begin = item;
-        item += (int64_t)M.tiles_per_xcd * N_XCD;
+        item += (int64_t)M.tiles_x * M.tiles_y;
         M.item_end = item;
     }
     h->n_items = item;
     h->tile_x = tx;
-    h->tile_h = th;
 }
 
 int32_t upload_members(lb_handle *h)
@@ -291,8 +288,8 @@ int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
 void free_graphs(lb_handle *h)
 {
     for (int p = 0; p < 2; ++p) {
-        if (h->graph[p]) hipGraphExecDestroy(h->graph[p]);
-        if (h->graph_src[p]) hipGraphDestroy(h->graph_src[p]);
+        if (h->graph[p]) (void)hipGraphExecDestroy(h->graph[p]);
+        if (h->graph_src[p]) (void)hipGraphDestroy(h->graph_src[p]);
         h->graph[p] = nullptr;
         h->graph_src[p] = nullptr;
     }
@@ -310,7 +307,7 @@ int32_t build_graphs(lb_handle *h)
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->capture, &g);
         if (rc != LB_OK) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return rc;
         }
         if (e != hipSuccess) return fail(LB_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
@@ -322,7 +319,7 @@ int32_t build_graphs(lb_handle *h)
 
 // Time `reps` steps that read the current buffer and write the other one
 // (state unchanged) with tile shape (tx, th); returns milliseconds per step.
-int32_t time_shape(lb_handle *h, int tx, int th, int reps, float &ms)
+int32_t time_shape(lb_handle *h, int tx, const std::vector<int> &th, int reps, float &ms)
 {
     plan_tiles(h, tx, th);
     int32_t rc = upload_members(h);
@@ -344,48 +341,72 @@ int32_t time_shape(lb_handle *h, int tx, int th, int reps, float &ms)
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipEventElapsedTime(&ms, a, b));
     ms /= (float)reps;
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     return LB_OK;
 }
 
+// Tile shapes.  Explicit tile_x / tile_h apply to every member.  Otherwise
+// each candidate width is tried with a coordinate search over one tile
+// height per member size class (members of equal nx, ny share it), timing
+// whole ensemble steps that read the current buffer and write the other one
+// (the state is unchanged).  The fastest combination is kept.
 int32_t choose_tiles(lb_handle *h)
 {
     const lb_config &c = h->cfg;
+    const size_t nm = h->dm.size();
     int64_t max_nx = 0, sites = 0;
     for (auto &M : h->dm) {
         max_nx = std::max<int64_t>(max_nx, M.nx);
         sites += (int64_t)M.nx * M.ny;
     }
     if (c.tile_x != 0) {
-        int th = c.tile_h > 0 ? c.tile_h : 64;
-        plan_tiles(h, c.tile_x, th);
+        plan_tiles(h, c.tile_x, std::vector<int>(nm, c.tile_h > 0 ? c.tile_h : 16));
         return upload_members(h);
     }
-    // candidates: widths no wider than the lattice needs, heights 16..256
-    std::vector<std::pair<int, int>> cand;
+    // size classes
+    std::vector<int> cls(nm);
+    std::vector<std::pair<int, int>> shapes;
+    for (size_t m = 0; m < nm; ++m) {
+        const std::pair<int, int> key{h->dm[m].nx, h->dm[m].ny};
+        auto it = std::find(shapes.begin(), shapes.end(), key);
+        cls[m] = (int)(it - shapes.begin());
+        if (it == shapes.end()) shapes.push_back(key);
+    }
+    std::vector<int> heights = {16, 32, 64, 128};
+    if (c.tile_h > 0) heights = {c.tile_h};
+    // about 20 ms of work per timing at ~20 GLUPS
+    const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(20, (int64_t)4e8 / std::max<int64_t>(sites, 1)));
+    float best = 1e30f;
+    int best_tx = 64;
+    std::vector<int> best_th(nm, heights.front());
     for (int tx : {64, 128, 256, 512}) {
         if (tx > 64 && tx / 2 >= max_nx) continue;
-        for (int th : {16, 32, 64, 128, 256}) {
-            if (c.tile_h > 0 && th != c.tile_h) continue;
-            cand.push_back({tx, th});
+        std::vector<int> hc(shapes.size(), heights.size() > 1 ? 32 : heights.front());
+        float cur_best = 1e30f;
+        for (size_t k = 0; k < shapes.size(); ++k) {
+            int keep = hc[k];
+            for (int th : heights) {
+                hc[k] = th;
+                std::vector<int> thm(nm);
+                for (size_t m = 0; m < nm; ++m) thm[m] = hc[cls[m]];
+                float ms = 0;
+                int32_t rc = time_shape(h, tx, thm, reps, ms);
+                if (rc) return rc;
+                if (ms < cur_best) {
+                    cur_best = ms;
+                    keep = th;
+                }
+            }
+            hc[k] = keep;
+        }
+        if (cur_best < best) {
+            best = cur_best;
+            best_tx = tx;
+            for (size_t m = 0; m < nm; ++m) best_th[m] = hc[cls[m]];
         }
     }
-    if (c.tile_h > 0 && cand.empty()) cand.push_back({64, c.tile_h});
-    // timing repetitions: about 50 ms of work per candidate at ~20 GLUPS
-    int reps = (int)std::max<int64_t>(2, std::min<int64_t>(20, (int64_t)1e9 / std::max<int64_t>(sites, 1)));
-    float best = 1e30f;
-    std::pair<int, int> best_shape = cand.front();
-    for (auto &sh : cand) {
-        float ms = 0;
-        int32_t rc = time_shape(h, sh.first, sh.second, reps, ms);
-        if (rc) return rc;
-        if (ms < best) {
-            best = ms;
-            best_shape = sh;
-        }
-    }
-    plan_tiles(h, best_shape.first, best_shape.second);
+    plan_tiles(h, best_tx, best_th);
     return upload_members(h);
 }
 
@@ -402,7 +423,8 @@ void set_scales(const lb_config *c, const lb_member &mm, Member &M)
             hi = std::max(hi, rho[k]);
             sum += rho[k];
         }
-        if (!(ref > 0)) ref = sum / (double)n;
+        if (ref == 0.0) ref = sum / (double)n;   // default: mean initial density
+        if (ref < 0.0) ref = 0.0;                 // negative: no shift
         for (int i = 0; i < NQ; ++i) {
             M.shift[s][i] = 0.0f;
             M.scale[s][i] = 1.0f;
@@ -465,7 +487,7 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
 
     auto bail = [&](int32_t code) {
         free_graphs(h);
-        if (h->capture) hipStreamDestroy(h->capture);
+        if (h->capture) (void)hipStreamDestroy(h->capture);
         delete h;
         return code;
     };
@@ -496,7 +518,7 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
         M.G = mm.G_AB;
         set_scales(cfg, mm, M);
     }
-    plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, cfg->tile_h ? cfg->tile_h : 64);
+    plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, std::vector<int>(cfg->n_members, cfg->tile_h ? cfg->tile_h : 16));
     if ((rc = upload_members(h))) return bail(rc);
 
     // initial state f(0) = w_i rho_s(0), written as the pre-streamed buffer
@@ -638,11 +660,12 @@ int64_t lb_time(const lb_handle *h)
     return h->t;
 }
 
-int32_t lb_tile_shape(const lb_handle *h, int32_t *tile_x, int32_t *tile_h)
+int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *tile_h)
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
     if (tile_x) *tile_x = h->tile_x;
-    if (tile_h) *tile_h = h->tile_h;
+    if (tile_h) *tile_h = h->dm[m].tile_h;
     return LB_OK;
 }
 
@@ -667,7 +690,7 @@ int32_t lb_destroy(lb_handle *h)
     }
     hipError_t e = hipStreamSynchronize(h->stream);
     free_graphs(h);
-    if (h->capture) hipStreamDestroy(h->capture);
+    if (h->capture) (void)hipStreamDestroy(h->capture);
     delete h;
     if (e != hipSuccess) return fail(LB_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
     return LB_OK;

@@ -8,7 +8,6 @@
 namespace lbk {
 
 constexpr int NQ = 9;
-constexpr int N_XCD = 8;     // MI355X: workgroups are dealt round-robin to 8 XCDs
 
 // One ensemble member as the kernels see it.  Lives in the workspace; every
 // field is uniform across a workgroup and read with scalar loads.
@@ -16,13 +15,12 @@ struct alignas(256) Member {
     int32_t nx, ny;          // lattice
     int32_t pitch;           // elements per stored row segment (nx rounded up to 64)
     int32_t tiles_x, tiles_y, tile_h;
-    int32_t tiles_per_xcd;   // tiles of this member handled by each of the 8 XCDs
     int64_t sstride;         // element strides of the population buffer:
     int64_t istride;         //   address of f_i^s(x, y) = s*sstride + i*istride
     int64_t ystride;         //                            + y*ystride + x
     int64_t item_begin;      // first work item of this member in the step launch
     int64_t item_end;
-    void *f[2];              // ping-pong population buffers, [s][i][y][pitch]
+    void *f[2];              // ping-pong population buffers, row blocks [y][s][i][pitch]
     double tau[2], itau[2];  // relaxation times and their reciprocals
     double G;                // Shan-Chen coupling
     double g[2][2];          // body acceleration per component

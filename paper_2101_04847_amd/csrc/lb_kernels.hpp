@@ -39,9 +39,6 @@
 #ifndef LBK_HALO_SPLIT
 #define LBK_HALO_SPLIT 1
 #endif
-#ifndef LBK_XCD_MAP
-#define LBK_XCD_MAP 0
-#endif
 #ifndef LBK_PIPE
 #define LBK_PIPE 1
 #endif
@@ -501,18 +498,8 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         while (m + 1 < n_members && members[m].item_end <= item) ++m;
         const Member &M = members[m];
         const int nx = M.nx, ny = M.ny;
-        // Work item -> tile.  Workgroup b runs on XCD b mod 8, each XCD with
-        // its own L2; the member's items start at a multiple of 8, so XCD k
-        // receives tiles [k Q, (k + 1) Q) of the row-major tile order: a
-        // horizontal band of the lattice whose neighbouring tiles share halo
-        // rows and columns through that L2.
-        const int64_t local = item - M.item_begin;
-#if LBK_XCD_MAP
-        const int64_t t = (int64_t)(local % N_XCD) * M.tiles_per_xcd + local / N_XCD;
-#else
-        const int64_t t = local;
-#endif
-        if (t >= (int64_t)M.tiles_x * M.tiles_y) continue;   // padding item (uniform)
+        // work item -> tile, row-major over the member's tiles
+        const int64_t t = item - M.item_begin;
         const int tx = (int)(t % M.tiles_x);
         const int ty = (int)(t / M.tiles_x);
         const int x0 = tx * TX;
@@ -623,7 +610,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
 
         // one march step: cf holds row r, nf the (requested) row r + 1; the
         // row r + 2 is requested into pf
-        auto step = [&](int r, C (&cf)[2][NQ], C (&nf)[2][NQ], C (&pf)[2][NQ]) {
+        auto march = [&](int r, C (&cf)[2][NQ], C (&nf)[2][NQ], C (&pf)[2][NQ]) {
             const int y = yfirst + dir * r;
             int yn = y + dir;                   // the row ahead
             const int sn = (r + 2) & 3;         // its ring slot
@@ -671,13 +658,13 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         // tracking of outstanding loads exact), then the remainder
         int r = 0;
         for (; r + 3 <= nrows; r += 3) {
-            step(r, fa, fb, fc);
-            step(r + 1, fb, fc, fa);
-            step(r + 2, fc, fa, fb);
+            march(r, fa, fb, fc);
+            march(r + 1, fb, fc, fa);
+            march(r + 2, fc, fa, fb);
         }
         if (r < nrows) {
-            step(r, fa, fb, fc);
-            if (r + 1 < nrows) step(r + 1, fb, fc, fa);
+            march(r, fa, fb, fc);
+            if (r + 1 < nrows) march(r + 1, fb, fc, fa);
         }
         } else {
         C cur_f[2][NQ], nxt_f[2][NQ];

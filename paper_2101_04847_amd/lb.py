@@ -74,7 +74,7 @@ _lib.lb_set_populations.argtypes = [_h, ctypes.c_int32, ctypes.c_void_p]
 _lib.lb_set_populations.restype = ctypes.c_int32
 _lib.lb_time.argtypes = [_h]
 _lib.lb_time.restype = ctypes.c_int64
-_lib.lb_tile_shape.argtypes = [_h, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+_lib.lb_tile_shape.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.lb_tile_shape.restype = ctypes.c_int32
 _lib.lb_storage_scale.argtypes = [_h, ctypes.c_int32, _dp, _dp]
 _lib.lb_storage_scale.restype = ctypes.c_int32
@@ -197,9 +197,9 @@ class Lattice:
     def t(self) -> int:
         return int(_lib.lb_time(self._h))
 
-    def tile_shape(self):
+    def tile_shape(self, m: int = 0):
         a, b = ctypes.c_int32(), ctypes.c_int32()
-        _check(_lib.lb_tile_shape(self._h, ctypes.byref(a), ctypes.byref(b)), "lb_tile_shape")
+        _check(_lib.lb_tile_shape(self._h, m, ctypes.byref(a), ctypes.byref(b)), "lb_tile_shape")
         return a.value, b.value
 
     def storage_scale(self, m: int = 0):

@@ -151,7 +151,7 @@ def test_tile_shape_does_not_change_results(lb):
     outs = []
     for tile in ((64, 4), (128, 16), (256, 64), (512, 3)):
         lat, _, _ = _pair(lb, 300, 50, tile=tile, seed=3)
-        assert lat.tile_shape() == tile
+        assert lat.tile_shape() == (tile[0], min(tile[1], 50))   # heights are clamped to ny
         lat.step(25)
         outs.append(lat.get_populations(0).cpu().numpy())
         d = lat.diagnostics(0)
