@@ -85,7 +85,7 @@ def release(lat):
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(wl, target_s: float = 20.0) -> dict:
+def cpu_baseline(wl, target_s: float = 15.0) -> dict:
     """The FP64 oracle on the host cores: full lattice, a few steps."""
     import oracle
     oracle.build(force=False)

@@ -12,6 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblb.so")
+PROBE = os.path.join(PKG, "bw_probe")
 SOURCES = [os.path.join(CSRC, "lb.hip")]
 HEADERS = [os.path.join(CSRC, "lb_kernels.hpp"), os.path.join(CSRC, "lb_internal.hpp"),
            os.path.join(ROOT, "include", "lb.h")]
@@ -39,6 +40,15 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(res.stdout + res.stderr)
         raise RuntimeError("hipcc failed building liblb.so")
     os.replace(tmp, LIB)
+    # the bandwidth probe (measured roofline denominator)
+    tmp = PROBE + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-o", tmp, os.path.join(CSRC, "bw_probe.hip")]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed building bw_probe")
+    os.replace(tmp, PROBE)
     return LIB
 
 
