@@ -1,19 +1,23 @@
 """Benchmark of the two-component D2Q9 Shan-Chen step on one MI355X.
 
-One step = one pass of the whole hot path over the lattice: pull-streaming
-with periodic x and bounce-back walls, densities and Shan-Chen + buoyancy
-forces, velocity-shift BGK collision, store.  Headline workload: the
-10000 x 5000 Rayleigh-Taylor lattice (tau = 1, G = 1.5, g = 1e-5, 32 seeded
-interface modes), FP64 storage and arithmetic, populations resident in HBM,
-100-step chunks replayed from HIP graphs.
+One step = the whole hot path over the lattice once: pull-streaming with
+periodic x and bounce-back walls, densities and Shan-Chen + buoyancy forces,
+velocity-shift BGK collision, store.  Headline workload: the 10000 x 5000
+Rayleigh-Taylor lattice (tau = 1, G = 1.5, g = 1e-5, 32 seeded interface
+modes), FP64 storage and arithmetic, populations resident in HBM, 100-step
+chunks replayed from HIP graphs.  The library times its two passes at
+initialisation and runs the faster per step: one step per kernel pass
+(k_step), or two steps fused in registers (k_step2, populations cross HBM
+once per two steps).
 
 Prints one JSON line: million lattice updates per second (MLUPS; one update
-= both components at one site for one step), the HBM roofline of the step
-kernel, the FP64 CPU oracle timed on a bounded sample of the same workload,
-the reduced-precision storage modes on the same lattice, and the 16-member
-batched ensemble (4 x 1024x512, 8 x 2048x1024, 4 x 4096x2048, FP32).
+= both components at one site for one step), the HBM roofline of the kernel
+that ran, the single-step pass on the same lattice, the FP64 CPU oracle timed
+on a bounded sample of the same workload, the reduced-precision storage
+modes, and the 16-member batched ensemble (4 x 1024x512, 8 x 2048x1024,
+4 x 4096x2048, FP32).
 
-    python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s]
+    python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s] [--spp 0|1|2]
     python bench.py --report out.json     # precision and ensemble studies
 """
 from __future__ import annotations
@@ -28,7 +32,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+# 2 components x 9 populations x (read + write) x element size: the bytes
+# one kernel pass moves per site (per lattice update for single steps)
 BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}
+KERNEL = {1: "step", 2: "step2"}
 METRIC = "MLUPS + % HBM peak, 2-comp D2Q9 Shan-Chen 10000×5000; ensemble MLUPS"
 
 
@@ -36,11 +43,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(storage: str, nx: int, ny: int):
-    """HBM bytes per step-kernel launch from the committed counter summary,
+def measured_traffic(kernel: str, storage: str, nx: int, ny: int):
+    """HBM bytes per launch of the kernel from the committed counter summary,
     if it was taken from the current kernel sources; else None."""
     from paper_2101_04847_amd.profiling import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", f"step_{storage}_{nx}x{ny}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_{nx}x{ny}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -54,13 +61,19 @@ def storage_code(lb, name):
     return {"f64": lb.F64, "f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[name]
 
 
-def lattice_for(lb, workloads, storage, tile=(0, 0), stream=None, graph_chunk=100):
+def lattice_for(lb, workloads, storage, tile=(0, 0), stream=None, graph_chunk=100, spp=0):
     members = []
     for wl in workloads:
         rA, rB = wl.densities()
         members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity))
     return lb.Lattice(members, forcing=lb.FORCE_SHIFT, storage=storage, tile_x=tile[0], tile_h=tile[1],
-                      graph_chunk=graph_chunk, stream=stream)
+                      graph_chunk=graph_chunk, stream=stream, steps_per_pass=spp)
+
+
+def hbm_frac(storage, spp, ms_step, sites):
+    """Fraction of the published HBM bandwidth that the pass's own bytes
+    (every population read and written once per pass) represent."""
+    return round(BYTES_PER_LU[storage] * sites / (ms_step * spp / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
 def time_steps(lat, steps, warmup, stream):
@@ -85,13 +98,14 @@ def release(lat):
     torch.cuda.empty_cache()
 
 
-def cpu_baseline(wl, target_s: float = 15.0) -> dict:
+def cpu_baseline(wl, target_s: float = 40.0) -> dict:
     """The FP64 oracle on the host cores: full lattice, a few steps."""
     import oracle
     oracle.build(force=False)
     rA, rB = wl.densities()
     p = oracle.Params(nx=wl.nx, ny=wl.ny, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
     f = oracle.fill_equilibrium(p, rA, rB)
+    oracle.run_inplace(p, f, 1)      # first touch of the buffers
     t0 = time.perf_counter()
     oracle.run_inplace(p, f, 1)
     one = time.perf_counter() - t0
@@ -102,33 +116,35 @@ def cpu_baseline(wl, target_s: float = 15.0) -> dict:
     del f
     return {"value": round(wl.nx * wl.ny * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
             "kind": "oracle",
-            "sample": f"{n} steps of the full {wl.nx}x{wl.ny} lattice after 1 untimed step "
+            "sample": f"{n} steps of the full {wl.nx}x{wl.ny} lattice after 2 untimed steps "
                       f"(FP64, OpenMP over rows, {dt:.1f} s)"}
 
 
-def variant_line(lb, inputs, name, stream, steps=300, warmup=50):
+def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0):
     wl = inputs.LARGE_10000x5000
-    lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream)
-    tile = lat.tile_shape()
+    lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream, spp=spp)
+    tile, got = lat.tile_shape(), lat.steps_per_pass
     ms, _ = time_steps(lat, steps, warmup, stream)
     release(lat)
-    mlups = wl.nx * wl.ny / (ms / 1e3) / 1e6
-    return {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "tile": list(tile),
-            "bytes_per_lu": BYTES_PER_LU[name],
-            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[name] / 1e9 / HBM_PEAK_GBS, 4)}
+    sites = wl.nx * wl.ny
+    mlups = sites / (ms / 1e3) / 1e6
+    return {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "steps_per_pass": got,
+            "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": BYTES_PER_LU[name] // got,
+            "hbm_frac": hbm_frac(name, got, ms, sites)}
 
 
 def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
     wls = inputs.ensemble_16()
     lat = lattice_for(lb, wls, storage_code(lb, storage), stream=stream)
     tiles = sorted({(wl.nx, wl.ny, *lat.tile_shape(k)) for k, wl in enumerate(wls)})
+    got = lat.steps_per_pass
     ms, _ = time_steps(lat, steps, warmup, stream)
     release(lat)
     sites = sum(wl.nx * wl.ny for wl in wls)
     mlups = sites / (ms / 1e3) / 1e6
     return {"members": len(wls), "sites": sites, "storage": storage, "MLUPS": round(mlups, 1),
-            "ms_per_step": round(ms, 4), "graph_chunk": 100,
-            "hbm_frac": round(mlups * 1e6 * BYTES_PER_LU[storage] / 1e9 / HBM_PEAK_GBS, 4),
+            "ms_per_step": round(ms, 4), "graph_chunk": 100, "steps_per_pass": got,
+            "kernel": "lbk::k_" + KERNEL[got], "hbm_frac": hbm_frac(storage, got, ms, sites),
             "tiles": [list(t) for t in tiles],
             "config": "4x1024x512 + 8x2048x1024 + 4x4096x2048, G alternating 0.5 / 1.5, seeds 100-115"}
 
@@ -140,6 +156,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_LU))
     ap.add_argument("--tile", default="", help="TXxH, e.g. 256x16 (default: timed choice)")
+    ap.add_argument("--spp", type=int, default=0, choices=(0, 1, 2),
+                    help="steps per kernel pass (0: timed choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the storage variants and the ensemble")
     ap.add_argument("--report", default="", help="run the precision / ensemble studies, write JSON here")
@@ -168,24 +186,32 @@ def main() -> int:
     if args.tile:
         a, b = args.tile.lower().split("x")
         tile = (int(a), int(b))
-    lat = lattice_for(lb, [wl], storage_code(lb, args.storage), tile=tile, stream=stream)
+    lat = lattice_for(lb, [wl], storage_code(lb, args.storage), tile=tile, stream=stream, spp=args.spp)
     tx, th = lat.tile_shape()
-    log(f"{wl.name} storage={args.storage} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
+    spp = lat.steps_per_pass
+    log(f"{wl.name} storage={args.storage} steps/pass={spp} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
     ms_step, wall = time_steps(lat, args.steps, args.warmup, stream)
     d = lat.diagnostics(0)
     release(lat)
     sites = wl.nx * wl.ny
     mlups = sites / (ms_step / 1e3) / 1e6
 
-    # roofline of the step kernel: one launch per step; algorithmic bytes =
-    # 2 components x 9 populations x (read + write) x element size per site
+    # roofline of the kernel that ran: one launch per pass of spp steps;
+    # algorithmic bytes per launch = 2 components x 9 populations x
+    # (read + write) x element size per site, i.e. BYTES_PER_LU / spp per
+    # lattice update
+    kernel = KERNEL[spp]
+    launch_ms = ms_step * spp
     alg_bytes = BYTES_PER_LU[args.storage] * sites
-    achieved = alg_bytes / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(args.storage, wl.nx, wl.ny)
+    achieved = alg_bytes / (launch_ms / 1e3) / 1e9
+    traffic = measured_traffic(kernel, args.storage, wl.nx, wl.ny)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_lu": BYTES_PER_LU[args.storage], "kernel": "lbk::k_step",
-            "launch_ms": round(ms_step, 4)}
+            "bytes_per_launch": alg_bytes, "bytes_per_lu": BYTES_PER_LU[args.storage] // spp,
+            "kernel": "lbk::k_" + kernel, "steps_per_launch": spp, "launch_ms": round(launch_ms, 4),
+            # the single-step method's 288 B per update at this rate (above
+            # the HBM peak when two steps are fused)
+            "effective_GBs": round(mlups * 1e6 * BYTES_PER_LU[args.storage] / 1e9, 1)}
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -193,12 +219,15 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "tau": wl.tau, "G_AB": wl.G, "g": wl.g,
-                   "forcing": "velocity-shift", "storage": args.storage, "tile": [tx, th],
-                   "graph_chunk": 100, "wall_s": round(wall, 3)},
+                   "forcing": "velocity-shift", "storage": args.storage, "steps_per_pass": spp,
+                   "tile": [tx, th], "graph_chunk": 100, "wall_s": round(wall, 3)},
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
     }
     if not args.no_extras:
+        if spp == 2:
+            log("single-step pass")
+            out["single_step"] = variant_line(lb, inputs, args.storage, stream, spp=1)
         out["storage_variants"] = []
         for name in ("f32", "f16s", "bf16s"):
             if name != args.storage:

@@ -110,6 +110,14 @@ typedef struct lb_config {
     int32_t tile_h;          /* rows per tile (>= 1); 0 chooses with tile_x */
     int32_t graph_chunk;     /* steps per captured HIP graph (even, >= 2);
                                 0 selects 100; negative disables graphs */
+    int32_t steps_per_pass;  /* time steps per kernel pass over the lattice:
+                                1, or 2 (two steps fused in registers, so the
+                                populations cross HBM once per two steps; an odd
+                                remainder of lb_step takes one single step; bit
+                                for bit the same result).  0 chooses by timing
+                                when tile_x == 0, else 1.  With 2, tile_x is
+                                ignored and tile_h (0 = timed) is the band
+                                height of the fused pass */
 } lb_config;
 
 /* Energy-budget averages at time t (Sec. 3, Eq. 15-18 and Eq. 22).  <.> is
@@ -172,10 +180,14 @@ int32_t lb_set_populations(lb_handle *h, int32_t m, const double *d_f);
 /* Completed steps (-1 if h is not a live handle). */
 int64_t lb_time(const lb_handle *h);
 
-/* Tile shape of member m: workgroup width in columns (shared by all members:
- * it is the block size of the single launch) and rows per tile (chosen per
- * member size class when tuned). */
+/* Tile shape of member m in the pass lb_step runs: columns per workgroup
+ * (shared by all members: one launch covers them all; 58 output columns per
+ * 64-lane wave for two-step passes) and rows per tile (chosen per member size
+ * class when tuned). */
 int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *tile_h);
+
+/* Time steps per kernel pass of lb_step: 1 or 2 (negative: error code). */
+int32_t lb_steps_per_pass(const lb_handle *h);
 
 /* Storage scale of member m for the 16-bit modes: scale[s*9 + i] receives
  * scale_{s,i} and shift[s*9 + i] receives w_i rho0_s (host arrays of 18;

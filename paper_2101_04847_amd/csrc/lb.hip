@@ -113,6 +113,26 @@ StepFn pick_step(int storage, int forcing, int bc, int k, bool fields)
     }
 }
 
+using Step2Fn = void (*)(const Member *, int, int64_t, int64_t, int);
+
+template <int ST>
+Step2Fn step2_for(int forcing, int bc)
+{
+    if (forcing == LB_FORCE_SHIFT)
+        return bc == LB_WALLS ? (Step2Fn)k_step2<ST, FORCE_SHIFT, BC_WALLS> : (Step2Fn)k_step2<ST, FORCE_SHIFT, BC_PERIODIC>;
+    return bc == LB_WALLS ? (Step2Fn)k_step2<ST, FORCE_GUO, BC_WALLS> : (Step2Fn)k_step2<ST, FORCE_GUO, BC_PERIODIC>;
+}
+
+Step2Fn pick_step2(int storage, int forcing, int bc)
+{
+    switch (storage) {
+        case LB_F64: return step2_for<ST_F64>(forcing, bc);
+        case LB_F32: return step2_for<ST_F32>(forcing, bc);
+        case LB_F16S: return step2_for<ST_F16S>(forcing, bc);
+        default: return step2_for<ST_BF16S>(forcing, bc);
+    }
+}
+
 template <int ST>
 ScatterFn scatter_for(int bc) { return bc == LB_WALLS ? k_scatter<ST, BC_WALLS> : k_scatter<ST, BC_PERIODIC>; }
 template <int ST>
@@ -193,6 +213,8 @@ int32_t validate(const lb_config *c)
     if (c->tile_h < 0) return fail(LB_EINVAL, "tile_h = %d must be >= 0", c->tile_h);
     if (c->graph_chunk > 0 && (c->graph_chunk % 2 != 0))
         return fail(LB_EINVAL, "graph_chunk = %d must be even", c->graph_chunk);
+    if (c->steps_per_pass < 0 || c->steps_per_pass > 2)
+        return fail(LB_EINVAL, "steps_per_pass = %d must be 0, 1 or 2", c->steps_per_pass);
     for (int m = 0; m < c->n_members; ++m) {
         const lb_member &mm = c->members[m];
         if (mm.nx < 3 || mm.ny < 3) return fail(LB_EINVAL, "member %d: nx = %d, ny = %d must be >= 3", m, mm.nx, mm.ny);
@@ -229,7 +251,10 @@ struct lb_handle {
     int cur = 0;
     int tile_x = 0;
     int64_t n_items = 0;
+    int steps_per_pass = 1;         // 2: lb_step runs the two-step pass
+    int64_t n_items2 = 0;
     int chunk = 0;
+    int chunk_flip = 0;             // buffer parity change of one graph replay
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipGraph_t graph_src[2] = {nullptr, nullptr};
     int device = 0;
@@ -266,14 +291,41 @@ void plan_tiles(lb_handle *h, int tx, const std::vector<int> &th)
     h->tile_x = tx;
 }
 
+// Bands of the two-step pass: TX2 output columns by th[m] rows.
+void plan_tiles2(lb_handle *h, const std::vector<int> &th)
+{
+    int64_t item = 0;
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        Member &M = h->dm[m];
+        M.tiles_x2 = (M.nx + TX2 - 1) / TX2;
+        M.tile_h2 = std::max(1, std::min(th[m], M.ny));
+        M.tiles_y2 = (M.ny + M.tile_h2 - 1) / M.tile_h2;
+        M.item2_begin = item;
+        item += (int64_t)M.tiles_x2 * M.tiles_y2;
+        M.item2_end = item;
+    }
+    h->n_items2 = item;
+}
+
 int32_t upload_members(lb_handle *h)
 {
     HIP_TRY(hipMemcpyAsync(dev_members(h), h->dm.data(), sizeof(Member) * h->dm.size(), hipMemcpyHostToDevice, h->stream));
     return LB_OK;
 }
 
+// n steps from buffer cur: two-step passes when selected (an odd remainder
+// takes one single step), else single steps.  Every pass reads buffer cur and
+// writes the other one.
 int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
 {
+    if (h->steps_per_pass == 2) {
+        Step2Fn fn2 = pick_step2(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y);
+        for (; n >= 2; n -= 2) {
+            hipLaunchKernelGGL(fn2, dim3((unsigned)h->n_items2), dim3(64), 0, s, (const Member *)dev_members(h),
+                               (int)h->dm.size(), (int64_t)0, h->n_items2, cur);
+            cur ^= 1;
+        }
+    }
     StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(h->tile_x), false);
     const FieldOut none{nullptr, nullptr, nullptr, nullptr};
     for (int64_t k = 0; k < n; ++k) {
@@ -304,6 +356,7 @@ int32_t build_graphs(lb_handle *h)
         HIP_TRY(hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
         int c = p;
         int32_t rc = launch_steps(h, h->capture, h->chunk, c);
+        h->chunk_flip = c ^ p;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->capture, &g);
         if (rc != LB_OK) {
@@ -346,11 +399,42 @@ int32_t time_shape(lb_handle *h, int tx, const std::vector<int> &th, int reps, f
     return LB_OK;
 }
 
+// Time `reps` two-step passes (read the current buffer, write the other one)
+// with band heights th; returns milliseconds per step (half a pass).
+int32_t time_shape2(lb_handle *h, const std::vector<int> &th, int reps, float &ms)
+{
+    plan_tiles2(h, th);
+    int32_t rc = upload_members(h);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    Step2Fn fn = pick_step2(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y);
+    auto once = [&]() {
+        hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items2), dim3(64), 0, h->stream, (const Member *)dev_members(h),
+                           (int)h->dm.size(), (int64_t)0, h->n_items2, h->cur);
+    };
+    once();  // warm-up
+    HIP_TRY(hipEventRecord(a, h->stream));
+    for (int r = 0; r < reps; ++r) once();
+    HIP_TRY(hipEventRecord(b, h->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    ms /= (float)(2 * reps);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return LB_OK;
+}
+
 // Tile shapes.  Explicit tile_x / tile_h apply to every member.  Otherwise
-// each candidate width is tried with a coordinate search over one tile
-// height per member size class (members of equal nx, ny share it), timing
-// whole ensemble steps that read the current buffer and write the other one
-// (the state is unchanged).  The fastest combination is kept.
+// each candidate is timed with a coordinate search over one tile height per
+// member size class (members of equal nx, ny share it), timing whole
+// ensemble passes that read the current buffer and write the other one (the
+// state is unchanged); the fastest is kept.  The single-step pass always
+// gets a shape (it serves odd remainders and the field pass); the two-step
+// pass is planned when it may be used, and with steps_per_pass == 0 the
+// faster of the two per step is selected.
 int32_t choose_tiles(lb_handle *h)
 {
     const lb_config &c = h->cfg;
@@ -359,10 +443,6 @@ int32_t choose_tiles(lb_handle *h)
     for (auto &M : h->dm) {
         max_nx = std::max<int64_t>(max_nx, M.nx);
         sites += (int64_t)M.nx * M.ny;
-    }
-    if (c.tile_x != 0) {
-        plan_tiles(h, c.tile_x, std::vector<int>(nm, c.tile_h > 0 ? c.tile_h : 16));
-        return upload_members(h);
     }
     // size classes
     std::vector<int> cls(nm);
@@ -373,17 +453,13 @@ int32_t choose_tiles(lb_handle *h)
         cls[m] = (int)(it - shapes.begin());
         if (it == shapes.end()) shapes.push_back(key);
     }
-    std::vector<int> heights = {16, 32, 64, 128};
-    if (c.tile_h > 0) heights = {c.tile_h};
     // about 20 ms of work per timing at ~20 GLUPS
     const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(20, (int64_t)4e8 / std::max<int64_t>(sites, 1)));
-    float best = 1e30f;
-    int best_tx = 64;
-    std::vector<int> best_th(nm, heights.front());
-    for (int tx : {64, 128, 256, 512}) {
-        if (tx > 64 && tx / 2 >= max_nx) continue;
-        std::vector<int> hc(shapes.size(), heights.size() > 1 ? 32 : heights.front());
-        float cur_best = 1e30f;
+    // coordinate search over per-class heights; time(thm, ms) times one shape
+    auto search = [&](const std::vector<int> &heights, int start, auto &&time_fn, std::vector<int> &best_th,
+                      float &best_ms) -> int32_t {
+        std::vector<int> hc(shapes.size(), heights.size() > 1 ? start : heights.front());
+        best_ms = 1e30f;
         for (size_t k = 0; k < shapes.size(); ++k) {
             int keep = hc[k];
             for (int th : heights) {
@@ -391,22 +467,61 @@ int32_t choose_tiles(lb_handle *h)
                 std::vector<int> thm(nm);
                 for (size_t m = 0; m < nm; ++m) thm[m] = hc[cls[m]];
                 float ms = 0;
-                int32_t rc = time_shape(h, tx, thm, reps, ms);
+                int32_t rc = time_fn(thm, ms);
                 if (rc) return rc;
-                if (ms < cur_best) {
-                    cur_best = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
                     keep = th;
                 }
             }
             hc[k] = keep;
         }
-        if (cur_best < best) {
-            best = cur_best;
-            best_tx = tx;
-            for (size_t m = 0; m < nm; ++m) best_th[m] = hc[cls[m]];
+        best_th.assign(nm, 0);
+        for (size_t m = 0; m < nm; ++m) best_th[m] = hc[cls[m]];
+        return LB_OK;
+    };
+    const int spp = c.steps_per_pass != 0 ? c.steps_per_pass : (c.tile_x != 0 ? 1 : 0);
+
+    // --- single-step pass
+    float best1 = 1e30f;
+    int best_tx = c.tile_x != 0 ? c.tile_x : 128;
+    std::vector<int> best_th(nm, c.tile_h > 0 ? c.tile_h : 16);
+    if (c.tile_x == 0 && spp != 2) {
+        std::vector<int> heights = {16, 32, 64, 128};
+        if (c.tile_h > 0) heights = {c.tile_h};
+        for (int tx : {64, 128, 256, 512}) {
+            if (tx > 64 && tx / 2 >= max_nx) continue;
+            std::vector<int> th;
+            float ms = 0;
+            int32_t rc = search(heights, 32, [&](const std::vector<int> &thm, float &t) {
+                return time_shape(h, tx, thm, reps, t);
+            }, th, ms);
+            if (rc) return rc;
+            if (ms < best1) {
+                best1 = ms;
+                best_tx = tx;
+                best_th = th;
+            }
         }
     }
     plan_tiles(h, best_tx, best_th);
+
+    // --- two-step pass
+    h->steps_per_pass = 1;
+    if (spp != 1) {
+        std::vector<int> th2(nm, c.tile_h > 0 ? c.tile_h : 12);
+        float best2 = 0.0f;
+        if (c.tile_h == 0 || spp == 0) {
+            std::vector<int> heights = {8, 12, 16, 24};
+            if (c.tile_h > 0) heights = {c.tile_h};
+            int32_t rc = search(heights, 12, [&](const std::vector<int> &thm, float &t) {
+                return time_shape2(h, thm, reps, t);
+            }, th2, best2);
+            if (rc) return rc;
+        }
+        plan_tiles2(h, th2);
+        if (spp == 2 || best2 < best1) h->steps_per_pass = 2;
+    }
     return upload_members(h);
 }
 
@@ -519,6 +634,7 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
         set_scales(cfg, mm, M);
     }
     plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, std::vector<int>(cfg->n_members, cfg->tile_h ? cfg->tile_h : 16));
+    plan_tiles2(h, std::vector<int>(cfg->n_members, 12));
     if ((rc = upload_members(h))) return bail(rc);
 
     // initial state f(0) = w_i rho_s(0), written as the pre-streamed buffer
@@ -560,7 +676,8 @@ int32_t lb_step(lb_handle *h, int64_t n)
     if (h->chunk > 0) {
         while (left >= h->chunk) {
             HIP_TRY(hipGraphLaunch(h->graph[h->cur], h->stream));
-            left -= h->chunk;  // chunk is even: the buffer parity is unchanged
+            h->cur ^= h->chunk_flip;
+            left -= h->chunk;
         }
     }
     int c = h->cur;
@@ -664,9 +781,15 @@ int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *t
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
-    if (tile_x) *tile_x = h->tile_x;
-    if (tile_h) *tile_h = h->dm[m].tile_h;
+    if (tile_x) *tile_x = h->steps_per_pass == 2 ? TX2 : h->tile_x;
+    if (tile_h) *tile_h = h->steps_per_pass == 2 ? h->dm[m].tile_h2 : h->dm[m].tile_h;
     return LB_OK;
+}
+
+int32_t lb_steps_per_pass(const lb_handle *h)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    return h->steps_per_pass;
 }
 
 int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *shift)

@@ -20,6 +20,10 @@ struct alignas(256) Member {
     int64_t ystride;         //                            + y*ystride + x
     int64_t item_begin;      // first work item of this member in the step launch
     int64_t item_end;
+    int32_t tiles_x2, tiles_y2, tile_h2;   // tiles of the two-step pass
+    int32_t pad_;
+    int64_t item2_begin;     // first work item of this member in the two-step launch
+    int64_t item2_end;
     void *f[2];              // ping-pong population buffers, row blocks [y][s][i][pitch]
     double tau[2], itau[2];  // relaxation times and their reciprocals
     double G;                // Shan-Chen coupling

@@ -46,6 +46,7 @@
 #define LBK_NT_STORE 1
 #endif
 
+
 namespace lbk {
 
 // ---------------------------------------------------------------------------
@@ -268,52 +269,40 @@ __device__ __forceinline__ void momentum(const C (&f)[NQ], double &jx, double &j
 }
 
 // ---------------------------------------------------------------------------
-// The fused step.  FIELDS = false: collide and store f*(t) into the other
-// buffer.  FIELDS = true: write rho_A, rho_B and the hydrodynamic velocity of
-// f(t) instead (no state change).  Work items are tiles of TX columns by
-// tile_h rows, numbered per member; a launch covers items [item0, item0 + n).
-// Force, collision and store (or field output) of one row for one lane:
-// Eq. 5 and 7 from the density ring, then Eq. 1-3 and the BGK relaxation of
-// Eq. 2 (or Guo forcing).  s0, sp, sm are the ring slots of rows y, y + 1 and
-// y - 1; e is this lane's ring column.
-template <int ST, int FORCING, bool FIELDS, int LW>
-__device__ __forceinline__ void row_update(const Member &M, const double (&ring)[4][2][LW], int s0, int sp, int sm,
-                                           int e, int x, int y, const typename Tr<ST>::C (&cur_f)[2][NQ],
-                                           const double (&rho_c)[2], void *dst, const FieldOut &fo)
+// Eq. 5 neighbour sum S = sum_i w_i psi(x + c_i) c_i of one component, in
+// index order (i = 1..8), from its eight neighbour densities p1..p8 (p_i at
+// x + c_i).
+__device__ __forceinline__ void sc_sum(double p1, double p2, double p3, double p4, double p5, double p6, double p7,
+                                       double p8, double &Sx, double &Sy)
 {
-    using Q = Tr<ST>;
-    using T = typename Q::T;
-    using C = typename Q::C;
-    const int nx = M.nx;
-    // Eq. 5 neighbour sums S_sbar = sum_i w_i psi_sbar(x + c_i) c_i
-    // for both components, in index order (i = 1..8).
-    double Sx[2], Sy[2];
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        const double p1 = ring[s0][o][e + 1];   // i = 1: (x+1, y)
-        const double p2 = ring[sp][o][e];       // i = 2: (x, y+1)
-        const double p3 = ring[s0][o][e - 1];   // i = 3: (x-1, y)
-        const double p4 = ring[sm][o][e];       // i = 4: (x, y-1)
-        const double p5 = ring[sp][o][e + 1];   // i = 5: (x+1, y+1)
-        const double p6 = ring[sp][o][e - 1];   // i = 6: (x-1, y+1)
-        const double p7 = ring[sm][o][e - 1];   // i = 7: (x-1, y-1)
-        const double p8 = ring[sm][o][e + 1];   // i = 8: (x+1, y-1)
-        const double w1 = wgt(1), w5 = wgt(5);
-        double sx = w1 * p1;
-        sx -= w1 * p3;
-        sx += w5 * p5;
-        sx -= w5 * p6;
-        sx -= w5 * p7;
-        sx += w5 * p8;
-        double sy = w1 * p2;
-        sy -= w1 * p4;
-        sy += w5 * p5;
-        sy += w5 * p6;
-        sy -= w5 * p7;
-        sy -= w5 * p8;
-        Sx[o] = sx;
-        Sy[o] = sy;
-    }
+    const double w1 = wgt(1), w5 = wgt(5);
+    double sx = w1 * p1;
+    sx -= w1 * p3;
+    sx += w5 * p5;
+    sx -= w5 * p6;
+    sx -= w5 * p7;
+    sx += w5 * p8;
+    double sy = w1 * p2;
+    sy -= w1 * p4;
+    sy += w5 * p5;
+    sy += w5 * p6;
+    sy -= w5 * p7;
+    sy -= w5 * p8;
+    Sx = sx;
+    Sy = sy;
+}
+
+// Collision of one site (Eq. 1-3 and the BGK relaxation of Eq. 2, or Guo
+// forcing) given the pulled populations cur_f, the densities rho_c and the
+// Shan-Chen sums S of the other component (S[s] belongs to component s, so
+// component s feels S[1 - s]).  Each post-collision value is handed to
+// emit(s, i, post) in the arithmetic type of the storage mode.
+template <int ST, int FORCING, class Emit>
+__device__ __forceinline__ void collide_site(const Member &M, const typename Tr<ST>::C (&cur_f)[2][NQ],
+                                             const double (&rho_c)[2], const double (&Sx)[2], const double (&Sy)[2],
+                                             Emit &&emit)
+{
+    using C = typename Tr<ST>::C;
     double jx[2], jy[2], Fx[2], Fy[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -323,18 +312,9 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
         Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
         Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
     }
-    const double rt = rho_c[0] + rho_c[1];
-    if constexpr (FIELDS) {
-        // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
-        const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
-        const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
-        const int64_t k = (int64_t)y * nx + x;
-        if (fo.rhoA) fo.rhoA[k] = rho_c[0];
-        if (fo.rhoB) fo.rhoB[k] = rho_c[1];
-        if (fo.ux) fo.ux[k] = ux;
-        if (fo.uy) fo.uy[k] = uy;
-    } else if constexpr (ST == ST_F64) {
+    if constexpr (ST == ST_F64) {
         // FP64: the definitions evaluated in their written order
+        const double rt = rho_c[0] + rho_c[1];
         double ux, uy;
         if (FORCING == FORCE_SHIFT) {
             // Eq. 1: velocity weighted by 1/tau_s
@@ -347,10 +327,6 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
             ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
             uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
         }
-        const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
-        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
-        const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
-        const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             double vxd = ux, vyd = uy;
@@ -393,19 +369,14 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
                     const C ey = (C)3 * ((C)cy(i) - guy) + (C)9 * cu * (C)cy(i);
                     post += gcoef * (C)wgt(i) * (ex * fx + ey * fy);
                 }
-                const T v = Q::enc(post, M.nss[s][i], M.scale[s][i]);
-                bstore<LBK_NT_STORE ? CPOL_NT : 0>(v, wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+                emit(s, i, post);
             }
         }
     } else {
         // Reduced-precision modes: the collision in FP32 with fused
-        // multiply-adds.  Densities and the Shan-Chen sums above stay FP64.
-        // With psi_s = rho_s the acceleration F_s / rho_s of Eq. 5 and 7 is
+        // multiply-adds.  Densities and the Shan-Chen sums stay FP64.  With
+        // psi_s = rho_s the acceleration F_s / rho_s of Eq. 5 and 7 is
         // -G S_sbar + g_s: no division.
-        const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
-        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
-        const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
-        const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
         float rf[2], ax[2], ay[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -446,13 +417,11 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
                 fy = r * ay[s];
                 uF = fmaf(ux, fx, uy * fy);
             }
-            const unsigned sb = (unsigned)s * wss;
             auto put = [&](int i, float fe, float src) {
                 const float fi = cur_f[s][i];
                 float post = fmaf(om, fe - fi, fi);          // Eq. 2
                 if (FORCING == FORCE_GUO) post += src;
-                bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
-                                                    sb + (unsigned)i * wis);
+                emit(s, i, post);
             };
             // rest population
             {
@@ -478,6 +447,57 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
             pair(5, 7, ux + uy, vx + vy, fx + fy);          // c = (1, 1)
             pair(8, 6, ux - uy, vx - vy, fx - fy);          // c = (1, -1)
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.  FIELDS = false: collide and store f*(t) into the other
+// buffer.  FIELDS = true: write rho_A, rho_B and the hydrodynamic velocity of
+// f(t) instead (no state change).  Work items are tiles of TX columns by
+// tile_h rows, numbered per member; a launch covers items [item0, item0 + n).
+// Force, collision and store (or field output) of one row for one lane:
+// Eq. 5 and 7 from the density ring, then collide_site.  s0, sp, sm are the
+// ring slots of rows y, y + 1 and y - 1; e is this lane's ring column.
+template <int ST, int FORCING, bool FIELDS, int LW>
+__device__ __forceinline__ void row_update(const Member &M, const double (&ring)[4][2][LW], int s0, int sp, int sm,
+                                           int e, int x, int y, const typename Tr<ST>::C (&cur_f)[2][NQ],
+                                           const double (&rho_c)[2], void *dst, const FieldOut &fo)
+{
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    using C = typename Q::C;
+    double Sx[2], Sy[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+        sc_sum(ring[s0][o][e + 1], ring[sp][o][e], ring[s0][o][e - 1], ring[sm][o][e], ring[sp][o][e + 1],
+               ring[sp][o][e - 1], ring[sm][o][e - 1], ring[sm][o][e + 1], Sx[o], Sy[o]);
+    if constexpr (FIELDS) {
+        double jx[2], jy[2], Fx[2], Fy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            momentum(cur_f[s], jx[s], jy[s]);
+            const double mg = -M.G * rho_c[s];
+            Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
+            Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
+        }
+        const double rt = rho_c[0] + rho_c[1];
+        // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
+        const double ux = (jx[0] + jx[1] + 0.5 * (Fx[0] + Fx[1])) / rt;
+        const double uy = (jy[0] + jy[1] + 0.5 * (Fy[0] + Fy[1])) / rt;
+        const int64_t k = (int64_t)y * M.nx + x;
+        if (fo.rhoA) fo.rhoA[k] = rho_c[0];
+        if (fo.rhoB) fo.rhoB[k] = rho_c[1];
+        if (fo.ux) fo.ux[k] = ux;
+        if (fo.uy) fo.uy[k] = uy;
+    } else {
+        const rsrc_t wr = row_rsrc(dst, y, M.ystride * (int64_t)sizeof(T));
+        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+        const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+        const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
+        collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, [&](int s, int i, C post) {
+            bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
+                                                (unsigned)s * wss + (unsigned)i * wis);
+        });
     }
 }
 
@@ -768,6 +788,278 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         }
         }
         __syncthreads();   // the ring is reused by the next item
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per pass (temporal blocking).
+//
+// A work item is one wave of 64 lanes; lane l holds column x0 - 3 + l (mod
+// nx).  It marches through a band of rows evaluating, per row, step t -> t+1
+// for all 64 columns (kept in registers, never stored) and, two rows behind,
+// step t+1 -> t+2, whose pulled populations come from the neighbouring
+// lanes' step-1 results.  Column neighbours (densities of both steps and the
+// x-streaming of step 2) move between lanes with DPP wavefront shifts, so the
+// pass needs no LDS and no barrier.  Lane l's step-1 result is valid for
+// l in [1, 62], its step-2 pull and density for [2, 61] and its step-2
+// result for [3, 60]: 58 output columns per item.  Every site goes through
+// collide_site exactly as in k_step (step-1 results pass through the storage
+// encoding), so one pass of two steps equals two passes of one step bit for
+// bit.  Populations are read once and written once per two steps; the price
+// is 4 extra step-1 rows per band and 6 extra step-1 columns per 58.
+constexpr int TX2 = 58;                 // output columns per work item
+constexpr int DPP_WAVE_SHL1 = 0x130;    // lane l receives lane l + 1 (column x + 1)
+constexpr int DPP_WAVE_SHR1 = 0x138;    // lane l receives lane l - 1 (column x - 1)
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+    const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)nhi << 32) | nlo);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v)
+{
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, false));
+}
+// value of the column to the left (x - 1) / right (x + 1)
+template <class V> __device__ __forceinline__ V from_left(V v) { return lane_shift<DPP_WAVE_SHR1>(v); }
+template <class V> __device__ __forceinline__ V from_right(V v) { return lane_shift<DPP_WAVE_SHL1>(v); }
+
+// Eq. 5 sums of both components from the densities of rows y - 1, y, y + 1
+// of this lane's column; the other columns come from the neighbouring lanes.
+__device__ __forceinline__ void sc_sums_lanes(const double (&lo)[2], const double (&mid)[2], const double (&hi)[2],
+                                              double (&Sx)[2], double (&Sy)[2])
+{
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+        sc_sum(from_right(mid[o]), hi[o], from_left(mid[o]), lo[o], from_right(hi[o]), from_left(hi[o]),
+               from_left(lo[o]), from_right(lo[o]), Sx[o], Sy[o]);
+}
+
+// Streamed value of population i for this lane's column from the same row
+// of step-1 results: shifted by c_x (bounce-back values are not shifted).
+template <int I, class V>
+__device__ __forceinline__ V shift_x(V v)
+{
+    if constexpr (cx(I) > 0) return from_left(v);
+    else if constexpr (cx(I) < 0) return from_right(v);
+    else return v;
+}
+
+// One band of the two-step pass, marching in direction DIR (+1: up).  Row
+// roles for the march index k (step-1 row a = first - 2 DIR + k DIR):
+//   step 1 collides row a (needs rho(t) of a - DIR, a, a + DIR);
+//   step 2 pulls row p = a - DIR from the step-1 rows a - 2 DIR (its c_y = DIR
+//   populations), p (c_y = 0) and a (c_y = -DIR), then collides row
+//   q = a - 2 DIR, whose densities rho(t+1) of q - DIR, q, q + DIR = p are then
+//   known.
+// The populations of row a + 2 DIR are requested right after the step-1
+// collision, into the registers it has just consumed (two rotating sets).
+// Only one pulled f(t+1) row is held in registers: row p's densities are
+// summed from its sources, and its populations are rebuilt (the same DPP
+// moves again) after the collision of row q.  This keeps the FP64 pass within
+// 256 VGPRs, two waves per SIMD.
+template <int ST, int FORCING, int BCY, int DIR>
+__device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nrows, int c, bool store_ok)
+{
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    using C = typename Q::C;
+    const int ny = M.ny;
+    const void *src = M.f[cur];
+    void *dst = M.f[cur ^ 1];
+    const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
+    const unsigned ox = (unsigned)c * (unsigned)sizeof(T);
+    const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+    const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
+    auto inside = [&](int v) { return BCY == BC_PERIODIC || (v >= 0 && v < ny); };
+    auto wrap = [&](int v) {
+        if (BCY == BC_PERIODIC) {
+            v %= ny;
+            if (v < 0) v += ny;
+        }
+        return v;
+    };
+    // populations whose source row lies ahead of (c_y = DIR) or behind
+    // (c_y = -DIR) the pulled row in the march
+    constexpr int FW[3] = {DIR > 0 ? 2 : 4, DIR > 0 ? 5 : 7, DIR > 0 ? 6 : 8};
+    constexpr int BW[3] = {DIR > 0 ? 4 : 2, DIR > 0 ? 7 : 5, DIR > 0 ? 8 : 6};
+
+    C fa[2][NQ], fb[2][NQ];     // pulled f(t) of rows a and a + DIR
+    C g[2][NQ];                 // pulled f(t+1) of row q (then of row p)
+    C P[2][NQ], Qv[2][NQ];      // step-1 results of rows a - DIR (c_y = 0, DIR) and a - 2 DIR (c_y = DIR)
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) fa[s][i] = fb[s][i] = g[s][i] = P[s][i] = Qv[s][i] = (C)0;
+    double r1m[2] = {0.0, 0.0}, r1c[2] = {0.0, 0.0};   // rho(t) of rows a - DIR, a
+    double r2m[2] = {0.0, 0.0}, r2c[2] = {0.0, 0.0};   // rho(t+1) of rows q - DIR, q
+
+    const int first = DIR > 0 ? y0 : y0 + nrows - 1;
+    const int a0 = first - 2 * DIR;
+    // prologue: densities of row a0 - DIR, row a0 in full, row a0 + DIR requested
+    if (inside(a0 - DIR)) {
+        C hf[2][NQ];
+        pull_site<ST, BCY>(src, M, wrap(a0 - DIR), c, hf);
+        r1m[0] = density(hf[0]);
+        r1m[1] = density(hf[1]);
+    }
+    if (inside(a0)) {
+        pull_site<ST, BCY>(src, M, wrap(a0), c, fa);
+        r1c[0] = density(fa[0]);
+        r1c[1] = density(fa[1]);
+    }
+    if (inside(a0 + DIR)) pull_site<ST, BCY>(src, M, wrap(a0 + DIR), c, fb);
+
+    // f1c: row a (then row a + 2 DIR); f1n: row a + DIR
+    auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
+        const int a = a0 + k * DIR;
+        const bool in_a = inside(a), in_am = inside(a - DIR), in_ap = inside(a + DIR);
+        // rho(t) of row a + DIR (its loads were issued one iteration ago)
+        const double r1n[2] = {density(f1n[0]), density(f1n[1])};
+        // --- step 1 at row a
+        C out1[2][NQ];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) out1[s][i] = (C)0;
+        if (in_a) {
+            // beyond a wall psi mirrors the wall row
+            double rb[2], rf[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                rb[s] = in_am ? r1m[s] : r1c[s];
+                rf[s] = in_ap ? r1n[s] : r1c[s];
+            }
+            double Sx[2], Sy[2];
+            if constexpr (DIR > 0) sc_sums_lanes(rb, r1c, rf, Sx, Sy);
+            else sc_sums_lanes(rf, r1c, rb, Sx, Sy);
+            collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, [&](int s, int i, C post) {
+                out1[s][i] = Q::dec(Q::enc(post, M.nss[s][i], M.scale[s][i]), M.shift[s][i], M.iscale[s][i]);
+            });
+        } else if (BCY == BC_WALLS) {
+            // row a lies beyond a wall: the pull of row a - DIR takes its
+            // c_y = -DIR populations from its own reversed ones (bounce-back)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) out1[s][BW[j]] = P[s][opp(BW[j])];
+        }
+        // request row a + 2 DIR into the registers just freed
+        if (inside(a + 2 * DIR)) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
+        // --- step 2: row p = a - DIR is pulled from the step-1 rows
+        const int p = a - DIR;
+        const bool pull_p = k >= 2 && inside(p);
+        const bool bb_f = (BCY == BC_WALLS) && !inside(p - DIR);   // Qv holds bounce-back values
+        const bool bb_b = (BCY == BC_WALLS) && !in_a;              // out1 holds bounce-back values
+        auto pull_row = [&](int s, C (&v)[NQ]) {
+            v[0] = P[s][0];
+            v[1] = shift_x<1>(P[s][1]);
+            v[3] = shift_x<3>(P[s][3]);
+            v[FW[0]] = Qv[s][FW[0]];
+            v[FW[1]] = bb_f ? Qv[s][FW[1]] : shift_x<FW[1]>(Qv[s][FW[1]]);
+            v[FW[2]] = bb_f ? Qv[s][FW[2]] : shift_x<FW[2]>(Qv[s][FW[2]]);
+            v[BW[0]] = out1[s][BW[0]];
+            v[BW[1]] = bb_b ? out1[s][BW[1]] : shift_x<BW[1]>(out1[s][BW[1]]);
+            v[BW[2]] = bb_b ? out1[s][BW[2]] : shift_x<BW[2]>(out1[s][BW[2]]);
+        };
+        // densities of row p (its populations are rebuilt after the
+        // collision of row q)
+        double r2n[2] = {0.0, 0.0};
+        if (pull_p) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                C v[NQ];
+                pull_row(s, v);
+                r2n[s] = density(v);
+            }
+        }
+        // --- step 2: collide row q = a - 2 DIR (inside the band from k = 4)
+        if (k >= 4) {
+            const int q = a - 2 * DIR;
+            double rb[2], rf[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                rb[s] = inside(q - DIR) ? r2m[s] : r2c[s];
+                rf[s] = inside(p) ? r2n[s] : r2c[s];
+            }
+            double Sx[2], Sy[2];
+            if constexpr (DIR > 0) sc_sums_lanes(rb, r2c, rf, Sx, Sy);
+            else sc_sums_lanes(rf, r2c, rb, Sx, Sy);
+            const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
+            collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, [&](int s, int i, C post) {
+                if (store_ok)
+                    bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
+                                                        (unsigned)s * wss + (unsigned)i * wis);
+            });
+        }
+        if (pull_p) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) pull_row(s, g[s]);
+        }
+        // --- rotate the step-1 results (row a becomes the previous row)
+        const bool bb_next = (BCY == BC_WALLS) && in_a && !in_am;   // row a is the first row at a wall
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Qv[s][FW[j]] = bb_next ? out1[s][opp(FW[j])] : P[s][FW[j]];
+            P[s][0] = out1[s][0];
+            P[s][1] = out1[s][1];
+            P[s][3] = out1[s][3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) P[s][FW[j]] = out1[s][FW[j]];
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            r1m[s] = r1c[s];
+            r1c[s] = r1n[s];
+            r2m[s] = r2c[s];
+            r2c[s] = r2n[s];
+        }
+    };
+    const int K = nrows + 4;
+    int k = 0;
+    for (; k + 2 <= K; k += 2) {
+        iter(k, fa, fb);
+        iter(k + 1, fb, fa);
+    }
+    if (k < K) iter(k, fa, fb);
+}
+
+// Two waves per SIMD: the FP64 pass then fits in 256 VGPRs without spills
+// (left alone the compiler takes a few more and drops to one wave); three
+// waves would need spills and measure much slower.
+template <int ST, int FORCING, int BCY>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur)
+{
+    const int lane = threadIdx.x;
+    for (int64_t item = item0 + blockIdx.x; item < item0 + n_items; item += gridDim.x) {
+        int m = 0;
+        while (m + 1 < n_members && members[m].item2_end <= item) ++m;
+        const Member &M = members[m];
+        const int64_t t = item - M.item2_begin;
+        const int tx = (int)(t % M.tiles_x2);
+        const int ty = (int)(t / M.tiles_x2);
+        const int x0 = tx * TX2;
+        const int y0 = ty * M.tile_h2;
+        const int nrows = min(M.tile_h2, M.ny - y0);
+        const int xl = x0 - 3 + lane;
+        int c = xl % M.nx;
+        if (c < 0) c += M.nx;
+        const bool store_ok = lane >= 3 && lane < 3 + TX2 && xl < M.nx;
+#if LBK_ALT_DIR
+        const bool down = (ty & 1) != 0;
+#else
+        const bool down = false;
+#endif
+        if (down) march2<ST, FORCING, BCY, -1>(M, cur, y0, nrows, c, store_ok);
+        else march2<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
     }
 }
 

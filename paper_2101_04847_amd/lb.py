@@ -46,7 +46,7 @@ class LbConfig(ctypes.Structure):
                 ("forcing", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("bc_y", ctypes.c_int32), ("diag_trim", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("graph_chunk", ctypes.c_int32)]
+                ("graph_chunk", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32)]
 
 
 class LbDiag(ctypes.Structure):
@@ -76,6 +76,8 @@ _lib.lb_time.argtypes = [_h]
 _lib.lb_time.restype = ctypes.c_int64
 _lib.lb_tile_shape.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
 _lib.lb_tile_shape.restype = ctypes.c_int32
+_lib.lb_steps_per_pass.argtypes = [_h]
+_lib.lb_steps_per_pass.restype = ctypes.c_int32
 _lib.lb_storage_scale.argtypes = [_h, ctypes.c_int32, _dp, _dp]
 _lib.lb_storage_scale.restype = ctypes.c_int32
 _lib.lb_destroy.argtypes = [_h]
@@ -85,7 +87,7 @@ _lib.lb_last_error.restype = ctypes.c_char_p
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
-           "lb_storage_scale", "lb_destroy", "lb_last_error")
+           "lb_steps_per_pass", "lb_storage_scale", "lb_destroy", "lb_last_error")
 
 
 class LBError(RuntimeError):
@@ -139,7 +141,7 @@ def _member_struct(m: Member, keep: list) -> LbMember:
 
 
 def make_config(members, forcing=FORCE_SHIFT, storage=F64, bc_y=WALLS, diag_trim=10, tile_x=0,
-                tile_h=0, graph_chunk=0):
+                tile_h=0, graph_chunk=0, steps_per_pass=0):
     """Build an LbConfig; returns (config, keepalive list)."""
     keep: list = []
     arr = (LbMember * len(members))(*[_member_struct(m, keep) for m in members])
@@ -149,6 +151,7 @@ def make_config(members, forcing=FORCE_SHIFT, storage=F64, bc_y=WALLS, diag_trim
     c.members = ctypes.cast(arr, ctypes.POINTER(LbMember))
     c.forcing, c.storage, c.bc_y = int(forcing), int(storage), int(bc_y)
     c.diag_trim, c.tile_x, c.tile_h, c.graph_chunk = int(diag_trim), int(tile_x), int(tile_h), int(graph_chunk)
+    c.steps_per_pass = int(steps_per_pass)
     return c, keep
 
 
@@ -167,12 +170,14 @@ class Lattice:
     ``stream`` (default: torch's current stream of that device)."""
 
     def __init__(self, members, forcing=FORCE_SHIFT, storage=F64, bc_y=WALLS, diag_trim=10,
-                 tile_x=0, tile_h=0, graph_chunk=0, device="cuda", stream=None, poison=False):
+                 tile_x=0, tile_h=0, graph_chunk=0, device="cuda", stream=None, poison=False,
+                 steps_per_pass=0):
         import torch
         self.members = list(members)
         self.storage, self.forcing, self.bc_y, self.diag_trim = storage, forcing, bc_y, diag_trim
         self.device = torch.device(device)
-        cfg, keep = make_config(self.members, forcing, storage, bc_y, diag_trim, tile_x, tile_h, graph_chunk)
+        cfg, keep = make_config(self.members, forcing, storage, bc_y, diag_trim, tile_x, tile_h, graph_chunk,
+                                steps_per_pass)
         nbytes = _lib.lb_workspace_bytes(ctypes.byref(cfg))
         if nbytes == 0:
             raise LBError(LB_EINVAL, "lb_workspace_bytes")
@@ -201,6 +206,13 @@ class Lattice:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.lb_tile_shape(self._h, m, ctypes.byref(a), ctypes.byref(b)), "lb_tile_shape")
         return a.value, b.value
+
+    @property
+    def steps_per_pass(self) -> int:
+        n = int(_lib.lb_steps_per_pass(self._h))
+        if n < 0:
+            raise LBError(n, "lb_steps_per_pass")
+        return n
 
     def storage_scale(self, m: int = 0):
         sc, sh = (ctypes.c_double * 18)(), (ctypes.c_double * 18)()

@@ -43,6 +43,7 @@ def test_header_constants_match_binding(lb):
     # struct sizes the binding assumes
     assert ctypes.sizeof(lb.LbMember) == 4 * 2 + 8 * 2 + 8 + 8 * 4 + 8 * 2 + 8 * 2
     assert ctypes.sizeof(lb.LbDiag) == 8 + 16 + 5 * 8 + 8
+    assert ctypes.sizeof(lb.LbConfig) == 4 + 4 + 8 + 8 * 4
 
 
 def _member(lb, nx=32, ny=30, **kw):
@@ -69,6 +70,8 @@ def test_workspace_bytes_accounts_for_storage(lb):
     (dict(diag_trim=0), "diag_trim"),
     (dict(tile_x=100), "tile_x"),
     (dict(graph_chunk=7), "graph_chunk"),
+    (dict(steps_per_pass=3), "steps_per_pass"),
+    (dict(steps_per_pass=-1), "steps_per_pass"),
 ])
 def test_config_validation(lb, kw, msg):
     c, _k = lb.make_config([_member(lb)], **kw)
@@ -114,6 +117,7 @@ def test_unknown_handle_is_rejected(lb):
     bogus = ctypes.c_void_p(0x1234)
     assert lb._lib.lb_step(bogus, 1) == lb.LB_ESTATE
     assert lb._lib.lb_time(bogus) == -1
+    assert lb._lib.lb_steps_per_pass(bogus) == lb.LB_ESTATE
     assert lb._lib.lb_destroy(bogus) == lb.LB_ESTATE
     assert lb._lib.lb_destroy(None) == lb.LB_ESTATE
     d = lb.LbDiag()
