@@ -186,9 +186,12 @@ static inline double psi_at(const orc_params *p, const double *rho_s, int y, int
     return rho_s[sidx(p, y, x)];
 }
 
-/* Eq. 5 + Eq. 7: F_s = -G rho_s sum_i w_i psi_sbar(x + c_i) c_i + rho_s g_s
- * (the fluid-boundary term of Eq. 6 vanishes for G_Ab = G_Bb = 0). */
-static void forces(const orc_params *p, const double *rho, double *Fx, double *Fy)
+/* Eq. 5 + Eq. 7 per unit mass: with psi_s = rho_s the force
+ * F_s = -G rho_s sum_i w_i psi_sbar(x + c_i) c_i + rho_s g_s is rho_s a_s
+ * with the acceleration a_s = -G sum_i w_i rho_sbar(x + c_i) c_i + g_s (the
+ * fluid-boundary term of Eq. 6 vanishes for G_Ab = G_Bb = 0).  This writes
+ * a_s; F_s = rho_s a_s where the force itself is needed. */
+static void accelerations(const orc_params *p, const double *rho, double *ax, double *ay)
 {
     const int nx = p->nx, ny = p->ny;
     const size_t n = (size_t)nx * ny;
@@ -203,13 +206,12 @@ static void forces(const orc_params *p, const double *rho, double *Fx, double *F
                     sx += W[i] * ps * CX[i];
                     sy += W[i] * ps * CY[i];
                 }
-                double r = rho[s * n + sidx(p, y, x)];
-                Fx[s * n + sidx(p, y, x)] = -p->G * r * sx + r * p->g[2 * s + 0];
-                Fy[s * n + sidx(p, y, x)] = -p->G * r * sy + r * p->g[2 * s + 1];
+                ax[s * n + sidx(p, y, x)] = -p->G * sx + p->g[2 * s + 0];
+                ay[s * n + sidx(p, y, x)] = -p->G * sy + p->g[2 * s + 1];
             }
 }
 
-/* Scratch layout used by one step: rho, jx, jy, Fx, Fy, each [2][ny][nx]. */
+/* Scratch layout used by one step: rho, jx, jy, ax, ay, each [2][ny][nx]. */
 size_t orc_scratch_doubles(const orc_params *p)
 {
     return (size_t)10 * (size_t)p->nx * (size_t)p->ny;
@@ -222,10 +224,12 @@ void orc_step(const orc_params *p, const double *f, double *fout, double *scratc
     const int nx = p->nx, ny = p->ny;
     const size_t n = (size_t)nx * ny;
     double *rho = scratch, *jx = scratch + 2 * n, *jy = scratch + 4 * n;
-    double *Fx = scratch + 6 * n, *Fy = scratch + 8 * n;
+    double *ax = scratch + 6 * n, *ay = scratch + 8 * n;
+    /* the factors 1/tau_s of Eq. 1 and Eq. 2 */
+    const double itau[2] = {1.0 / p->tau[0], 1.0 / p->tau[1]};
 
     moments(p, f, rho, jx, jy);
-    forces(p, rho, Fx, Fy);
+    accelerations(p, rho, ax, ay);
 
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -234,29 +238,33 @@ void orc_step(const orc_params *p, const double *f, double *fout, double *scratc
             const double rA = rho[k], rB = rho[n + k];
             /* Velocities entering the equilibrium. */
             double ux, uy;
+            /* F_s = rho_s a_s */
+            const double FxA = rA * ax[k], FxB = rB * ax[n + k];
+            const double FyA = rA * ay[k], FyB = rB * ay[n + k];
             if (p->forcing == 0) {
                 /* Eq. 1: common velocity weighted by 1/tau_s. */
-                double num_x = jx[k] / p->tau[0] + jx[n + k] / p->tau[1];
-                double num_y = jy[k] / p->tau[0] + jy[n + k] / p->tau[1];
-                double den = rA / p->tau[0] + rB / p->tau[1];
+                double num_x = jx[k] * itau[0] + jx[n + k] * itau[1];
+                double num_y = jy[k] * itau[0] + jy[n + k] * itau[1];
+                double den = rA * itau[0] + rB * itau[1];
                 ux = num_x / den;
                 uy = num_y / den;
             } else {
                 /* Guo: common velocity including half the total force. */
                 double rt = rA + rB;
-                ux = (jx[k] + jx[n + k] + 0.5 * (Fx[k] + Fx[n + k])) / rt;
-                uy = (jy[k] + jy[n + k] + 0.5 * (Fy[k] + Fy[n + k])) / rt;
+                ux = (jx[k] + jx[n + k] + 0.5 * (FxA + FxB)) / rt;
+                uy = (jy[k] + jy[n + k] + 0.5 * (FyA + FyB)) / rt;
             }
             for (int s = 0; s < 2; ++s) {
                 const double r = rho[s * n + k];
-                const double fx = Fx[s * n + k], fy = Fy[s * n + k];
+                const double fx = s == 0 ? FxA : FxB, fy = s == 0 ? FyA : FyB;
                 const double tau = p->tau[s];
-                const double omega = 1.0 / tau; /* the factor 1/tau_s of Eq. 2 */
+                const double omega = itau[s];
                 double vx = ux, vy = uy;
                 if (p->forcing == 0) {
-                    /* Eq. 3: shifted velocity u' = u + tau_s F_s / rho_s. */
-                    vx = ux + tau * fx / r;
-                    vy = uy + tau * fy / r;
+                    /* Eq. 3: shifted velocity u' = u + tau_s F_s / rho_s
+                     * = u + tau_s a_s. */
+                    vx = ux + tau * ax[s * n + k];
+                    vy = uy + tau * ay[s * n + k];
                 }
                 double feq[NQ];
                 orc_equilibrium(r, vx, vy, feq);
@@ -325,17 +333,20 @@ int orc_macro(const orc_params *p, const double *f, double *rhoA, double *rhoB, 
     double *scratch = (double *)malloc(orc_scratch_doubles(p) * sizeof(double));
     if (!scratch) return -1;
     double *rho = scratch, *jx = scratch + 2 * n, *jy = scratch + 4 * n;
-    double *Fx = scratch + 6 * n, *Fy = scratch + 8 * n;
+    double *ax = scratch + 6 * n, *ay = scratch + 8 * n;
     moments(p, f, rho, jx, jy);
-    forces(p, rho, Fx, Fy);
+    accelerations(p, rho, ax, ay);
     for (size_t k = 0; k < n; ++k) {
         double rt = rho[k] + rho[n + k];
+        /* F_s = rho_s a_s */
+        const double FxA = rho[k] * ax[k], FxB = rho[n + k] * ax[n + k];
+        const double FyA = rho[k] * ay[k], FyB = rho[n + k] * ay[n + k];
         if (rhoA) rhoA[k] = rho[k];
         if (rhoB) rhoB[k] = rho[n + k];
-        if (ux) ux[k] = (jx[k] + jx[n + k] + 0.5 * (Fx[k] + Fx[n + k])) / rt;
-        if (uy) uy[k] = (jy[k] + jy[n + k] + 0.5 * (Fy[k] + Fy[n + k])) / rt;
-        if (Ftx) Ftx[k] = Fx[k] + Fx[n + k];
-        if (Fty) Fty[k] = Fy[k] + Fy[n + k];
+        if (ux) ux[k] = (jx[k] + jx[n + k] + 0.5 * (FxA + FxB)) / rt;
+        if (uy) uy[k] = (jy[k] + jy[n + k] + 0.5 * (FyA + FyB)) / rt;
+        if (Ftx) Ftx[k] = FxA + FxB;
+        if (Fty) Fty[k] = FyA + FyB;
     }
     free(scratch);
     return 0;

@@ -303,24 +303,28 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
                                              Emit &&emit)
 {
     using C = typename Tr<ST>::C;
-    double jx[2], jy[2], Fx[2], Fy[2];
+    double jx[2], jy[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        momentum(cur_f[s], jx[s], jy[s]);
-        // F_s = -G rho_s S_sbar + rho_s g_s   (Eq. 5 + Eq. 7)
-        const double mg = -M.G * rho_c[s];
-        Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
-        Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
-    }
+    for (int s = 0; s < 2; ++s) momentum(cur_f[s], jx[s], jy[s]);
     if constexpr (ST == ST_F64) {
-        // FP64: the definitions evaluated in their written order
+        // FP64: the definitions evaluated in their written order.  With
+        // psi_s = rho_s, Eq. 5 + Eq. 7 give F_s = rho_s a_s with the
+        // acceleration a_s = -G S_sbar + g_s.
+        double ax[2], ay[2], Fx[2], Fy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            ax[s] = -M.G * Sx[1 - s] + M.g[s][0];
+            ay[s] = -M.G * Sy[1 - s] + M.g[s][1];
+            Fx[s] = rho_c[s] * ax[s];
+            Fy[s] = rho_c[s] * ay[s];
+        }
         const double rt = rho_c[0] + rho_c[1];
         double ux, uy;
         if (FORCING == FORCE_SHIFT) {
             // Eq. 1: velocity weighted by 1/tau_s
-            const double nxv = jx[0] / M.tau[0] + jx[1] / M.tau[1];
-            const double nyv = jy[0] / M.tau[0] + jy[1] / M.tau[1];
-            const double den = rho_c[0] / M.tau[0] + rho_c[1] / M.tau[1];
+            const double nxv = jx[0] * M.itau[0] + jx[1] * M.itau[1];
+            const double nyv = jy[0] * M.itau[0] + jy[1] * M.itau[1];
+            const double den = rho_c[0] * M.itau[0] + rho_c[1] * M.itau[1];
             ux = nxv / den;
             uy = nyv / den;
         } else {
@@ -331,9 +335,9 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
         for (int s = 0; s < 2; ++s) {
             double vxd = ux, vyd = uy;
             if (FORCING == FORCE_SHIFT) {
-                // Eq. 3: shifted velocity u + tau_s F_s / rho_s
-                vxd = ux + M.tau[s] * Fx[s] / rho_c[s];
-                vyd = uy + M.tau[s] * Fy[s] / rho_c[s];
+                // Eq. 3: shifted velocity u + tau_s F_s / rho_s = u + tau_s a_s
+                vxd = ux + M.tau[s] * ax[s];
+                vyd = uy + M.tau[s] * ay[s];
             }
             const C vx = (C)vxd, vy = (C)vyd, rho = (C)rho_c[s];
             const C omega = (C)M.itau[s];
@@ -374,9 +378,8 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
         }
     } else {
         // Reduced-precision modes: the collision in FP32 with fused
-        // multiply-adds.  Densities and the Shan-Chen sums stay FP64.  With
-        // psi_s = rho_s the acceleration F_s / rho_s of Eq. 5 and 7 is
-        // -G S_sbar + g_s: no division.
+        // multiply-adds.  Densities, the Shan-Chen sums and the
+        // accelerations a_s = -G S_sbar + g_s stay FP64.
         float rf[2], ax[2], ay[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -476,9 +479,9 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             momentum(cur_f[s], jx[s], jy[s]);
-            const double mg = -M.G * rho_c[s];
-            Fx[s] = mg * Sx[1 - s] + rho_c[s] * M.g[s][0];
-            Fy[s] = mg * Sy[1 - s] + rho_c[s] * M.g[s][1];
+            // F_s = rho_s a_s, a_s = -G S_sbar + g_s   (Eq. 5 + Eq. 7, psi_s = rho_s)
+            Fx[s] = rho_c[s] * (-M.G * Sx[1 - s] + M.g[s][0]);
+            Fy[s] = rho_c[s] * (-M.G * Sy[1 - s] + M.g[s][1]);
         }
         const double rt = rho_c[0] + rho_c[1];
         // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
