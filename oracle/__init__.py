@@ -6,8 +6,10 @@ library never imports, links or calls anything in this directory, and this
 module imports nothing from the GPU package.
 
 The oracle implements one time step of the two-component D2Q9 Shan-Chen
-lattice Boltzmann model of Sec. 2 of the paper (Eq. 1-7) in push form, and the
-energy-budget averages of Sec. 3 (Eq. 15-18, Eq. 22).  Arrays follow the
+lattice Boltzmann model of Sec. 2 of the paper (Eq. 1-7) in push form, the
+energy-budget averages of Sec. 3 (Eq. 15-18, Eq. 22) and, in ``budget.py``,
+the momentum-flux and viscous terms of the kinetic-energy balance
+(Eq. 11-14, 17-19).  Arrays follow the
 layout f[s][i][y][x] (s = A, B; i = 0..8), densities and velocities [y][x].
 """
 from __future__ import annotations
@@ -211,3 +213,13 @@ def diagnostics(p: Params, f: np.ndarray, trim: int = 10, profile: bool = False)
     if profile:
         d["phi_profile"] = prof
     return d
+
+
+def energy_budget(p: Params, f: np.ndarray, trim: int = 10) -> dict:
+    """Kinetic-energy budget terms (Eq. 17-19) of the state f: the fields of
+    ``macro`` passed to ``budget.budget_from_fields`` with tau the mean of
+    tau_A and tau_B."""
+    from .budget import budget_from_fields
+    m = macro(p, f)
+    tau = 0.5 * (float(p.tau[0]) + float(p.tau[1]))
+    return budget_from_fields(m["rhoA"], m["rhoB"], m["ux"], m["uy"], float(p.G), tau, trim)

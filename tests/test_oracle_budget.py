@@ -1,0 +1,152 @@
+"""Pins of the energy-budget oracle (oracle/budget.py, Eq. 11-14 and 17-19).
+
+The oracle evaluates the terms with centred finite differences.  Each pin
+compares it with a different form of the same continuum quantity, evaluated
+with exact (spectral) derivatives on a lattice whose trimmed domain D spans
+whole periods of smooth trigonometric fields, so the two agree to the O(k^2)
+error of the centred differences:
+  * Korteweg: the identity div P^K = -kappa phi grad(lap phi) that the paper
+    uses in Eq. 20 (a dropped or mis-signed term of Eq. 13 breaks it);
+  * bulk pressure: p_b written as c_s^2 rho + G c_s^2 rho_A rho_B (Eq. 12
+    with rho^2 - phi^2 = 4 rho_A rho_B);
+  * tau term: h = grad ln(rho_A / rho_B) (Eq. 14);
+  * viscous term: integrated by parts, -<|grad u|^2> - <(div u)^2>;
+and, exactly, the discrete form of Eq. 22 for a Taylor-Green flow:
+<u . div(grad u + grad u^T)> = -<omega^2>, with <omega^2> from the C
+oracle's diagnostics of the same state.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import budget
+
+N = 256          # periodic extent of D in x and y
+TRIM = 2
+K = 2.0 * np.pi / N
+CS2 = 1.0 / 3.0
+
+
+def _grid():
+    ny = N + 2 * TRIM
+    x = np.arange(N, dtype=np.float64)[None, :]
+    y = (np.arange(ny, dtype=np.float64) - TRIM)[:, None]   # y = 0 at the first row of D
+    return x, y
+
+
+def _fields():
+    """Smooth periodic fields whose products share Fourier modes with div u
+    and the stress components, so that no average vanishes by symmetry."""
+    x, y = _grid()
+    A, U = 0.4, 0.02
+    phi = A * (np.sin(K * x) * np.sin(K * y) + 0.5 * np.cos(K * x + 0.3))
+    rho = 1.0 + 0.05 * (np.cos(2 * K * x) + np.sin(2 * K * y + 0.2))
+    ux = U * (np.sin(2 * K * x) + 0.5 * np.sin(2 * K * x) * np.cos(2 * K * y) + 0.3 * np.cos(K * y)
+              + 0.8 * np.sin(2 * K * y))
+    uy = U * (np.sin(2 * K * y) + 0.4 * np.cos(2 * K * x + 0.1) * np.sin(2 * K * y))
+    ones = np.ones_like(x * y)
+    return 0.5 * (rho + phi) * ones, 0.5 * (rho - phi) * ones, ux * ones, uy * ones
+
+
+def _d(q, axis):
+    """Exact derivative of a periodic N x N field (FFT)."""
+    n = q.shape[axis]
+    kk = 2.0 * np.pi * np.fft.fftfreq(n)
+    shape = [1, 1]
+    shape[axis] = n
+    return np.real(np.fft.ifft(1j * kk.reshape(shape) * np.fft.fft(q, axis=axis), axis=axis))
+
+
+def _D(q):
+    """Restrict a lattice field to the periodic domain D."""
+    return q[TRIM:TRIM + N]
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+G, TAU = 1.5, 0.8
+
+
+def test_korteweg_term_matches_eq20_identity():
+    rA, rB, ux, uy = _fields()
+    got = budget.budget_from_fields(rA, rB, ux, uy, G, TAU, trim=TRIM)["korteweg"]
+    phi = _D(rA - rB)
+    kappa = CS2 * CS2 * G / 4.0
+    lap = _d(_d(phi, 1), 1) + _d(_d(phi, 0), 0)
+    want = np.mean(-kappa * phi * (_D(ux) * _d(lap, 1) + _D(uy) * _d(lap, 0)))
+    assert _rel(got, want) < 3e-3, (got, want)
+
+
+def test_bulk_pressure_term():
+    rA, rB, ux, uy = _fields()
+    got = budget.budget_from_fields(rA, rB, ux, uy, G, TAU, trim=TRIM)["pb"]
+    a, b = _D(rA), _D(rB)
+    p = CS2 * (a + b) + G * CS2 * a * b
+    want = np.mean(_D(ux) * _d(p, 1) + _D(uy) * _d(p, 0))
+    assert _rel(got, want) < 3e-3, (got, want)
+
+
+def test_tau_term():
+    rA, rB, ux, uy = _fields()
+    got = budget.budget_from_fields(rA, rB, ux, uy, G, TAU, trim=TRIM)["ktau"]
+    a, b = _D(rA), _D(rB)
+    lr = np.log(a / b)
+    hx, hy = _d(lr, 1), _d(lr, 0)
+    c = CS2 * CS2 * (a * b / (a + b)) * (TAU - 0.5) ** 2
+    divx = _d(c * hx * hx, 1) + _d(c * hx * hy, 0)
+    divy = _d(c * hx * hy, 1) + _d(c * hy * hy, 0)
+    want = np.mean(_D(ux) * divx + _D(uy) * divy)
+    assert _rel(got, want) < 3e-3, (got, want)
+
+
+def test_viscous_term_by_parts():
+    rA, rB, ux, uy = _fields()
+    out = budget.budget_from_fields(rA, rB, ux, uy, G, TAU, trim=TRIM)
+    u, v = _D(ux), _D(uy)
+    gu = [_d(u, 1), _d(u, 0), _d(v, 1), _d(v, 0)]
+    div = gu[0] + gu[3]
+    want = -np.mean(sum(g * g for g in gu)) - np.mean(div * div)
+    assert _rel(out["V"], want) < 3e-3, (out["V"], want)
+    rho_mean = np.mean(rA + rB)
+    assert out["viscous"] == pytest.approx(rho_mean * CS2 * (TAU - 0.5) * out["V"], rel=1e-14)
+
+
+def test_taylor_green_dissipation_equals_enstrophy_term():
+    """Eq. 22 on the lattice: for u = U (sin kx cos ky, -cos kx sin ky) the
+    centred differences make u discretely divergence-free and
+    <u . div(grad u + grad u^T)> = -<omega^2> exactly (= -U^2 sin^2 k)."""
+    n, trim, U = 64, 2, 0.01
+    k = 2.0 * np.pi / 16
+    ny = n + 2 * trim
+    x = np.arange(n, dtype=np.float64)[None, :]
+    y = (np.arange(ny, dtype=np.float64) - trim)[:, None]
+    ux = U * np.sin(k * x) * np.cos(k * y) * np.ones((ny, 1))
+    uy = -U * np.cos(k * x) * np.sin(k * y) * np.ones((1, n))
+    rA = np.full((ny, n), 0.5)
+    rB = np.full((ny, n), 0.5)
+    p = oracle.Params(nx=n, ny=ny, tau=(1.0, 1.0), G=0.0, g=((0.0, 0.0), (0.0, 0.0)))
+    f = oracle.fill_equilibrium(p, rA, rB, ux, uy)
+    m = oracle.macro(p, f)
+    out = budget.budget_from_fields(m["rhoA"], m["rhoB"], m["ux"], m["uy"], 0.0, 1.0, trim=trim)
+    om2 = oracle.diagnostics(p, f, trim=trim)["omega2"]
+    assert out["V"] == pytest.approx(-om2, rel=1e-12)
+    assert out["V"] == pytest.approx(-U * U * np.sin(k) ** 2, rel=1e-12)
+    for key in ("pb", "korteweg", "ktau"):
+        assert abs(out[key]) < 1e-18
+
+
+def test_uniform_state_has_no_fluxes():
+    ny, nx = 20, 16
+    z = np.zeros((ny, nx))
+    out = budget.budget_from_fields(np.full((ny, nx), 0.7), np.full((ny, nx), 0.3), z + 0.01, z - 0.02, 1.5, 1.0,
+                                    trim=2)
+    for key in ("pb", "korteweg", "ktau", "V"):
+        assert out[key] == 0.0
+
+
+def test_trim_below_two_is_rejected():
+    z = np.ones((10, 8))
+    with pytest.raises(ValueError):
+        budget.budget_from_fields(z, z, z, z, 1.0, 1.0, trim=1)
