@@ -192,6 +192,16 @@ def main() -> int:
     log(f"{wl.name} storage={args.storage} steps/pass={spp} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
     ms_step, wall = time_steps(lat, args.steps, args.warmup, stream)
     d = lat.diagnostics(0)
+    # cost of the analysis passes (each call synchronises): energy-budget
+    # averages and the kinetic-energy balance terms, best of three
+    t_diag, t_budget = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        lat.diagnostics(0)
+        t_diag.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        budget = lat.energy_budget(0)
+        t_budget.append(time.perf_counter() - t0)
     release(lat)
     sites = wl.nx * wl.ny
     mlups = sites / (ms_step / 1e3) / 1e6
@@ -223,6 +233,8 @@ def main() -> int:
                    "tile": [tx, th], "graph_chunk": 100, "wall_s": round(wall, 3)},
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
+        "analysis_ms": {"diagnostics": round(min(t_diag) * 1e3, 3), "energy_budget": round(min(t_budget) * 1e3, 3),
+                        "budget": {k: budget[k] for k in ("pb", "korteweg", "ktau", "viscous", "buoyancy")}},
     }
     if not args.no_extras:
         if spp == 2:

@@ -168,7 +168,31 @@ int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, doubl
  * (after filling *out) if a density or velocity is not finite. */
 int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profile);
 
-/* Populations f(t) of member m, decoded to FP64, into a caller device buffer
+/* Terms of the kinetic-energy balance (Sec. 3, Eq. 17) of member m at time t,
+ * averaged like lb_diag over the trimmed domain D, from the fields of
+ * lb_fields by centred differences (d_x q = (q(x+1) - q(x-1))/2, x periodic;
+ * five-point Laplacian; (div T)_b = d_x T_xb + d_y T_yb):
+ *   dE_k/dt = -(pb + korteweg + ktau) + viscous - buoyancy,
+ * the momentum-flux split of Eq. 19 with P = p_b I + P^K + K^(tau) (Eq. 11). */
+typedef struct lb_budget {
+    int64_t t;
+    double pb;               /* <u . grad p_b>, p_b = c_s^2 rho + (G c_s^2/4)(rho^2 - phi^2) (Eq. 12) */
+    double korteweg;         /* <u . div P^K>, P^K = [-kappa phi lap phi - (kappa/2)|grad phi|^2] I
+                                + kappa grad phi (x) grad phi, kappa = c_s^4 G / 4 (Eq. 13) */
+    double ktau;             /* <u . div K^(tau)>, K^(tau) = c_s^4 (rho_A rho_B / rho)(tau - 1/2)^2 h (x) h,
+                                h = grad rho_A / rho_A - grad rho_B / rho_B (Eq. 14) */
+    double viscous;          /* <u . div(eta grad u + eta grad u^T)> (Eq. 17) */
+    double eta;              /* eta = mean(rho) c_s^2 (tau - 1/2), tau = (tau_A + tau_B)/2 */
+    double buoyancy;         /* as lb_diag.buoyancy */
+} lb_budget;
+
+/* Energy-budget terms of member m (see lb_budget) into *out (host).  Needs
+ * diag_trim >= 2 (the stencils reach two rows; LB_EINVAL otherwise).  Uses
+ * the same workspace field buffer as lb_diagnostics.  Synchronises the
+ * stream. */
+int32_t lb_energy_budget(lb_handle *h, int32_t m, lb_budget *out);
+
+/* Populations f(t) of member m, decoded to FP64, into a caller device buffer/* Populations f(t) of member m, decoded to FP64, into a caller device buffer
  * of 2*9*ny*nx doubles, layout [s][i][y][x].  Asynchronous. */
 int32_t lb_get_populations(lb_handle *h, int32_t m, double *d_f);
 

@@ -739,6 +739,53 @@ int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profil
     return LB_OK;
 }
 
+int32_t lb_energy_budget(lb_handle *h, int32_t m, lb_budget *out)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    if (h->cfg.diag_trim < 2)
+        return fail(LB_EINVAL, "the budget stencils reach two rows: diag_trim = %d must be >= 2", h->cfg.diag_trim);
+    const Member &M = h->dm[m];
+    const lb_member &mm = h->mem[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    double *fld = (double *)(h->ws + h->L.fields);
+    int32_t rc = lb_fields(h, m, fld, fld + n, fld + 2 * n, fld + 3 * n);
+    if (rc) return rc;
+    // the paper's Eq. 14 and viscosity carry one tau: the mean of tau_A, tau_B
+    const double tau = 0.5 * (mm.tau[0] + mm.tau[1]);
+    BudgetConst K;
+    K.cs2 = 1.0 / 3.0;
+    K.gc = mm.G_AB * K.cs2 / 4.0;
+    K.kappa = K.cs2 * K.cs2 * mm.G_AB / 4.0;
+    K.c0 = K.cs2 * K.cs2;
+    K.tf = (tau - 0.5) * (tau - 0.5);
+    K.gA[0] = mm.g[0][0];
+    K.gA[1] = mm.g[0][1];
+    K.gB[0] = mm.g[1][0];
+    K.gB[1] = mm.g[1][1];
+    double *part = (double *)(h->ws + h->L.part);
+    double *red = (double *)(h->ws + h->L.red);
+    const int nb = (M.ny - 2 * h->cfg.diag_trim + BT_R - 1) / BT_R;   // bands of D rows (<= ny)
+    hipLaunchKernelGGL(k_budget_rows, dim3(nb), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, K, part);
+    hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nb, red);
+    HIP_TRY(hipGetLastError());
+    double host[BUDGET_NQ];
+    HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double nd = (double)M.nx * (double)(M.ny - 2 * h->cfg.diag_trim);
+    out->t = h->t;
+    out->pb = host[1] / nd;
+    out->korteweg = host[2] / nd;
+    out->ktau = host[3] / nd;
+    const double rho_mean = host[0] / (double)n;
+    out->eta = rho_mean * K.cs2 * (tau - 0.5);
+    out->viscous = out->eta * (host[4] / nd);
+    out->buoyancy = host[5] / nd;
+    return LB_OK;
+}
+
 int32_t lb_get_populations(lb_handle *h, int32_t m, double *d_f)
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");

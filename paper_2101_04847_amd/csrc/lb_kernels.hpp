@@ -1217,6 +1217,162 @@ k_reduce_rows(const double *__restrict__ fld, int nx, int ny, int trim, double g
     }
 }
 
+// ---------------------------------------------------------------------------
+// Kinetic-energy budget of Sec. 3 (Eq. 11-14, 17-19) from the field buffer
+// by centred differences: d_x q = (q(x+1) - q(x-1)) / 2 (x periodic), d_y
+// likewise, the five-point Laplacian, and the divergence of a tensor
+// (div T)_b = d_x T_xb + d_y T_yb with the tensor formed at each site.  The
+// terms reach two rows and columns away (trim >= 2).  Each site's
+// expressions are evaluated in a fixed order:
+//   pb    u . grad p_b,  p_b = c_s^2 rho + (G c_s^2 / 4)(rho^2 - phi^2)         (Eq. 12)
+//   kort  u . div P^K,   P^K = [-kappa phi lap phi - (kappa/2)|grad phi|^2] I
+//                              + kappa grad phi (x) grad phi                    (Eq. 13)
+//   ktau  u . div K,     K = c_s^4 (rho_A rho_B / rho)(tau - 1/2)^2 h (x) h,
+//                        h = grad rho_A / rho_A - grad rho_B / rho_B           (Eq. 14)
+//   V     u . div(grad u + grad u^T)   (the viscous term of Eq. 17 over eta)
+// Per band of rows: sum rho, then over the sites of D: sum pb, sum kort,
+// sum ktau, sum V, sum -u . (rho_A gA + rho_B gB).
+struct BudgetConst {
+    double cs2;     // c_s^2
+    double gc;      // G c_s^2 / 4
+    double kappa;   // c_s^4 G / 4
+    double c0;      // c_s^4
+    double tf;      // (tau - 1/2)^2
+    double gA[2], gB[2];
+};
+constexpr int BUDGET_NQ = 6;
+constexpr int BT_W = 64;        // output columns of a tile
+constexpr int BT_R = 4;         // output rows of a tile (BT_W * BT_R = RED_THREADS)
+static_assert(BT_W * BT_R == RED_THREADS, "one thread per output site of a tile");
+
+// One workgroup per band of BT_R rows of D; it walks the band in tiles of
+// BT_W columns.  Per tile: (1) the four fields on the tile plus two halo rows
+// and columns go to LDS; (2) the tensors p_b, P^K, K and grad u + grad u^T
+// are formed once at every point of the tile plus one halo row and column;
+// (3) each thread takes the divergences at its site.  part[band][q] as for
+// the row kernel: [0] sums rho over the band's rows (the first and last
+// bands also cover the trimmed rows), [1..5] the budget terms over D.
+__global__ void __launch_bounds__(RED_THREADS)
+k_budget_rows(const double *__restrict__ fld, int nx, int ny, int trim, BudgetConst K, double *__restrict__ part)
+{
+    constexpr int FW = BT_W + 4, FR = BT_R + 4;   // field tile with two halo columns / rows per side
+    constexpr int TW = BT_W + 2, TR = BT_R + 2;   // tensor tile with one halo
+    __shared__ double sf[4][FR][FW];              // rho_A, rho_B, u_x, u_y
+    __shared__ double st[10][TR][TW];             // p_b, Pxx, Pxy, Pyy, Kxx, Kxy, Kyy, Sxx, Sxy, Syy
+    __shared__ double sh[RED_THREADS / 64];
+    const int64_t n = (int64_t)nx * ny;
+    const int nD = ny - 2 * trim;
+    const int nb = (nD + BT_R - 1) / BT_R;
+    const int b = blockIdx.x;
+    const int y0 = trim + b * BT_R;               // first output row of the band
+    const int tid = threadIdx.x;
+    double a[BUDGET_NQ] = {0, 0, 0, 0, 0, 0};
+
+    // [0]: total density over the band's rows (whole lattice over all bands)
+    {
+        const int lo = b == 0 ? 0 : y0, hi = b == nb - 1 ? ny : min(y0 + BT_R, ny - trim);
+        for (int64_t k = (int64_t)lo * nx + tid; k < (int64_t)hi * nx; k += RED_THREADS) a[0] += fld[k] + fld[n + k];
+    }
+    const int ty = tid / BT_W, tx = tid % BT_W;
+    for (int x0 = 0; x0 < nx; x0 += BT_W) {
+        // (1) fields of rows y0-2 .. y0+BT_R+1 and columns x0-2 .. x0+BT_W+1;
+        // rows beyond the lattice only feed non-output rows and are clamped
+        for (int e = tid; e < FR * FW; e += RED_THREADS) {
+            const int r = e / FW, cc = e % FW;
+            const int yy = min(max(y0 - 2 + r, 0), ny - 1);
+            int xx = (x0 - 2 + cc) % nx;
+            if (xx < 0) xx += nx;
+            const int64_t k = (int64_t)yy * nx + xx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sf[q][r][cc] = fld[q * n + k];
+        }
+        __syncthreads();
+        // (2) tensors at tile rows -1 .. BT_R and columns -1 .. BT_W
+        for (int e = tid; e < TR * TW; e += RED_THREADS) {
+            const int r = e / TW + 1, cc = e % TW + 1;    // position in the field tile
+            auto A = [&](int dr, int dc) { return sf[0][r + dr][cc + dc]; };
+            auto B = [&](int dr, int dc) { return sf[1][r + dr][cc + dc]; };
+            auto phi = [&](int dr, int dc) { return A(dr, dc) - B(dr, dc); };
+            auto rho = [&](int dr, int dc) { return A(dr, dc) + B(dr, dc); };
+            const int o = e / TW, w = e % TW;
+            {
+                const double rr = rho(0, 0), pp = phi(0, 0);
+                st[0][o][w] = K.cs2 * rr + K.gc * (rr * rr - pp * pp);
+            }
+            {
+                const double gx = 0.5 * (phi(0, 1) - phi(0, -1)), gy = 0.5 * (phi(1, 0) - phi(-1, 0));
+                const double lap = phi(0, 1) + phi(0, -1) + phi(1, 0) + phi(-1, 0) - 4.0 * phi(0, 0);
+                const double iso = -K.kappa * phi(0, 0) * lap - 0.5 * K.kappa * (gx * gx + gy * gy);
+                st[1][o][w] = iso + K.kappa * gx * gx;
+                st[2][o][w] = K.kappa * gx * gy;
+                st[3][o][w] = iso + K.kappa * gy * gy;
+            }
+            {
+                const double ra = A(0, 0), rb = B(0, 0);
+                const double hx = 0.5 * (A(0, 1) - A(0, -1)) / ra - 0.5 * (B(0, 1) - B(0, -1)) / rb;
+                const double hy = 0.5 * (A(1, 0) - A(-1, 0)) / ra - 0.5 * (B(1, 0) - B(-1, 0)) / rb;
+                const double c = K.c0 * (ra * rb / (ra + rb)) * K.tf;
+                st[4][o][w] = c * hx * hx;
+                st[5][o][w] = c * hx * hy;
+                st[6][o][w] = c * hy * hy;
+            }
+            {
+                auto U = [&](int dr, int dc) { return sf[2][r + dr][cc + dc]; };
+                auto V = [&](int dr, int dc) { return sf[3][r + dr][cc + dc]; };
+                st[7][o][w] = 2.0 * (0.5 * (U(0, 1) - U(0, -1)));
+                st[9][o][w] = 2.0 * (0.5 * (V(1, 0) - V(-1, 0)));
+                st[8][o][w] = 0.5 * (V(0, 1) - V(0, -1)) + 0.5 * (U(1, 0) - U(-1, 0));
+            }
+        }
+        __syncthreads();
+        // (3) divergences at this thread's site
+        const int y = y0 + ty, x = x0 + tx;
+        if (y < ny - trim && x < nx) {
+            const int o = ty + 1, w = tx + 1;
+            const double u = sf[2][ty + 2][tx + 2], v = sf[3][ty + 2][tx + 2];
+            auto div = [&](int cxx, int cxy, int cyy, double &dvx, double &dvy) {
+                dvx = 0.5 * (st[cxx][o][w + 1] - st[cxx][o][w - 1]) + 0.5 * (st[cxy][o + 1][w] - st[cxy][o - 1][w]);
+                dvy = 0.5 * (st[cxy][o][w + 1] - st[cxy][o][w - 1]) + 0.5 * (st[cyy][o + 1][w] - st[cyy][o - 1][w]);
+            };
+            a[1] += u * (0.5 * (st[0][o][w + 1] - st[0][o][w - 1])) + v * (0.5 * (st[0][o + 1][w] - st[0][o - 1][w]));
+            double dvx, dvy;
+            div(1, 2, 3, dvx, dvy);
+            a[2] += u * dvx + v * dvy;
+            div(4, 5, 6, dvx, dvy);
+            a[3] += u * dvx + v * dvy;
+            div(7, 8, 9, dvx, dvy);
+            a[4] += u * dvx + v * dvy;
+            const double ra = sf[0][ty + 2][tx + 2], rb = sf[1][ty + 2][tx + 2];
+            const double fy = ra * K.gA[1] + rb * K.gB[1];
+            const double fx = ra * K.gA[0] + rb * K.gB[0];
+            a[5] += -(u * fx + v * fy);
+        }
+        __syncthreads();   // the tiles are rewritten for the next x0
+    }
+#pragma unroll
+    for (int q = 0; q < BUDGET_NQ; ++q) {
+        const double r = block_combine<false>(a[q], sh);
+        if (tid == 0) part[(int64_t)b * RED_NQ + q] = r;
+    }
+}
+
+// out[0..BUDGET_NQ) = part[][q] summed over the nb bands in a fixed order.
+__global__ void __launch_bounds__(RED_THREADS)
+k_budget_final(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    double a[BUDGET_NQ] = {0, 0, 0, 0, 0, 0};
+    for (int y = threadIdx.x; y < nb; y += RED_THREADS) {
+#pragma unroll
+        for (int q = 0; q < BUDGET_NQ; ++q) a[q] += part[(int64_t)y * RED_NQ + q];
+    }
+#pragma unroll
+    for (int q = 0; q < BUDGET_NQ; ++q) {
+        const double r = block_combine<false>(a[q], sh);
+        if (threadIdx.x == 0) out[q] = r;
+    }
+}
+
 // out[0..8] as part[] summed over rows (max for [7]); prof[y] = row mean of phi.
 __global__ void __launch_bounds__(RED_THREADS)
 k_reduce_final(const double *__restrict__ part, int nx, int ny, double *__restrict__ out, double *__restrict__ prof)

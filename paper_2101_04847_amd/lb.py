@@ -56,6 +56,12 @@ class LbDiag(ctypes.Structure):
                 ("umax", ctypes.c_double), ("finite", ctypes.c_int32)]
 
 
+class LbBudget(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("pb", ctypes.c_double), ("korteweg", ctypes.c_double),
+                ("ktau", ctypes.c_double), ("viscous", ctypes.c_double), ("eta", ctypes.c_double),
+                ("buoyancy", ctypes.c_double)]
+
+
 _h = ctypes.c_void_p
 _lib.lb_workspace_bytes.argtypes = [ctypes.POINTER(LbConfig)]
 _lib.lb_workspace_bytes.restype = ctypes.c_size_t
@@ -68,6 +74,8 @@ _lib.lb_fields.argtypes = [_h, ctypes.c_int32] + [ctypes.c_void_p] * 4
 _lib.lb_fields.restype = ctypes.c_int32
 _lib.lb_diagnostics.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbDiag), _dp]
 _lib.lb_diagnostics.restype = ctypes.c_int32
+_lib.lb_energy_budget.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbBudget)]
+_lib.lb_energy_budget.restype = ctypes.c_int32
 _lib.lb_get_populations.argtypes = [_h, ctypes.c_int32, ctypes.c_void_p]
 _lib.lb_get_populations.restype = ctypes.c_int32
 _lib.lb_set_populations.argtypes = [_h, ctypes.c_int32, ctypes.c_void_p]
@@ -85,7 +93,7 @@ _lib.lb_destroy.restype = ctypes.c_int32
 _lib.lb_last_error.argtypes = []
 _lib.lb_last_error.restype = ctypes.c_char_p
 
-EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics",
+EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_energy_budget",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
            "lb_steps_per_pass", "lb_storage_scale", "lb_destroy", "lb_last_error")
 
@@ -242,6 +250,13 @@ class Lattice:
         if profile:
             out["phi_profile"] = prof
         return out
+
+    def energy_budget(self, m: int = 0) -> dict:
+        """Terms of the kinetic-energy balance (lb_budget): pb, korteweg,
+        ktau, viscous, eta, buoyancy and t."""
+        b = LbBudget()
+        _check(_lib.lb_energy_budget(self._h, m, ctypes.byref(b)), "lb_energy_budget")
+        return {k: getattr(b, k) for k, _ in LbBudget._fields_}
 
     def get_populations(self, m: int = 0):
         import torch

@@ -44,6 +44,7 @@ def test_header_constants_match_binding(lb):
     assert ctypes.sizeof(lb.LbMember) == 4 * 2 + 8 * 2 + 8 + 8 * 4 + 8 * 2 + 8 * 2
     assert ctypes.sizeof(lb.LbDiag) == 8 + 16 + 5 * 8 + 8
     assert ctypes.sizeof(lb.LbConfig) == 4 + 4 + 8 + 8 * 4
+    assert ctypes.sizeof(lb.LbBudget) == 8 + 6 * 8
 
 
 def _member(lb, nx=32, ny=30, **kw):
@@ -122,6 +123,8 @@ def test_unknown_handle_is_rejected(lb):
     assert lb._lib.lb_destroy(None) == lb.LB_ESTATE
     d = lb.LbDiag()
     assert lb._lib.lb_diagnostics(bogus, 0, ctypes.byref(d), None) == lb.LB_ESTATE
+    b = lb.LbBudget()
+    assert lb._lib.lb_energy_budget(bogus, 0, ctypes.byref(b)) == lb.LB_ESTATE
     assert lb._lib.lb_fields(bogus, 0, None, None, None, None) == lb.LB_ESTATE
     assert "live" in lb.last_error()
 
