@@ -192,7 +192,36 @@ typedef struct lb_budget {
  * stream. */
 int32_t lb_energy_budget(lb_handle *h, int32_t m, lb_budget *out);
 
-/* Populations f(t) of member m, decoded to FP64, into a caller device buffer/* Populations f(t) of member m, decoded to FP64, into a caller device buffer
+/* Interface phi = rho_A - rho_B = 0 of member m at time t (Sec. 3, Eq. 20-21):
+ * crossings of the lattice lines, counted as neighbouring site pairs with
+ * phi > 0 at exactly one site, both sites in the trimmed domain D (x
+ * periodic), and the Cauchy-Crofton length of the interface inside D. */
+typedef struct lb_interface {
+    int64_t t;
+    int64_t crossings[4];    /* along rows (x, x+1), columns (y, y+1), and the
+                                diagonals (x, y)-(x+1, y+1) and (x+1, y)-(x, y+1) */
+    double length;           /* (pi/8) [N_rows + N_cols + (N_diag1 + N_diag2) / sqrt(2)] */
+} lb_interface;
+
+/* Interface crossings and length of member m (see lb_interface) into *out
+ * (host).  Uses the workspace field buffer.  Synchronises the stream. */
+int32_t lb_interface_length(lb_handle *h, int32_t m, lb_interface *out);
+
+/* Topology of the two phases of member m at time t (Sec. 3): the numbers of
+ * connected components of the A-rich set phi > 0 and of its complement
+ * phi <= 0 inside the trimmed domain D, sites joined to their row and column
+ * neighbours of the same phase, x periodic. */
+typedef struct lb_topology {
+    int64_t t;
+    int64_t components[2];   /* [0]: phi > 0, [1]: phi <= 0 */
+} lb_topology;
+
+/* Component counts of member m (see lb_topology) into *out (host).  Uses
+ * the workspace field buffer (the densities and 4 B per site of D for the
+ * union-find parents).  Synchronises the stream. */
+int32_t lb_components(lb_handle *h, int32_t m, lb_topology *out);
+
+/* Populations f(t) of member m, decoded to FP64, into a caller device buffer
  * of 2*9*ny*nx doubles, layout [s][i][y][x].  Asynchronous. */
 int32_t lb_get_populations(lb_handle *h, int32_t m, double *d_f);
 

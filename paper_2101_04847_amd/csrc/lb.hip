@@ -769,7 +769,7 @@ int32_t lb_energy_budget(lb_handle *h, int32_t m, lb_budget *out)
     const int nb = (M.ny - 2 * h->cfg.diag_trim + BT_R - 1) / BT_R;   // bands of D rows (<= ny)
     hipLaunchKernelGGL(k_budget_rows, dim3(nb), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
                        h->cfg.diag_trim, K, part);
-    hipLaunchKernelGGL(k_budget_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nb, red);
+    hipLaunchKernelGGL(k_sum_rows<BUDGET_NQ>, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nb, red);
     HIP_TRY(hipGetLastError());
     double host[BUDGET_NQ];
     HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, h->stream));
@@ -783,6 +783,69 @@ int32_t lb_energy_budget(lb_handle *h, int32_t m, lb_budget *out)
     out->eta = rho_mean * K.cs2 * (tau - 0.5);
     out->viscous = out->eta * (host[4] / nd);
     out->buoyancy = host[5] / nd;
+    return LB_OK;
+}
+
+int32_t lb_interface_length(lb_handle *h, int32_t m, lb_interface *out)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    const Member &M = h->dm[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    double *fld = (double *)(h->ws + h->L.fields);
+    int32_t rc = lb_fields(h, m, fld, fld + n, nullptr, nullptr);
+    if (rc) return rc;
+    double *part = (double *)(h->ws + h->L.part);
+    double *red = (double *)(h->ws + h->L.red);
+    const int nD = M.ny - 2 * h->cfg.diag_trim;
+    hipLaunchKernelGGL(k_interface_rows, dim3(nD), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, part);
+    hipLaunchKernelGGL(k_sum_rows<IFACE_NQ>, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nD, red);
+    HIP_TRY(hipGetLastError());
+    double host[IFACE_NQ];
+    HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    out->t = h->t;
+    for (int q = 0; q < IFACE_NQ; ++q) out->crossings[q] = (int64_t)host[q];
+    // Cauchy-Crofton: rows and columns are 1 apart, diagonals 1/sqrt(2)
+    out->length = M_PI / 8.0 * ((double)(out->crossings[0] + out->crossings[1]) +
+                                (double)(out->crossings[2] + out->crossings[3]) / std::sqrt(2.0));
+    return LB_OK;
+}
+
+int32_t lb_components(lb_handle *h, int32_t m, lb_topology *out)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    const Member &M = h->dm[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    const int nD = M.ny - 2 * h->cfg.diag_trim;
+    const int64_t nsites = (int64_t)nD * M.nx;
+    double *fld = (double *)(h->ws + h->L.fields);
+    // densities in the first half of the field buffer, the union-find
+    // parents (4 B per site of D) in the velocity half
+    int32_t rc = lb_fields(h, m, fld, fld + n, nullptr, nullptr);
+    if (rc) return rc;
+    int *parent = (int *)(fld + 2 * n);
+    double *part = (double *)(h->ws + h->L.part);
+    double *red = (double *)(h->ws + h->L.red);
+    const unsigned grid = (unsigned)std::min<int64_t>((nsites + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, h->stream, parent, nsites);
+    hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(256), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, parent);
+    hipLaunchKernelGGL(k_cc_rows, dim3(nD), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, (const int *)parent, part);
+    hipLaunchKernelGGL(k_sum_rows<3>, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nD, red);
+    HIP_TRY(hipGetLastError());
+    double host[3];
+    HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (host[2] != 0.0) return fail(LB_EHIP, "component labelling left %.0f edges unjoined", host[2]);
+    out->t = h->t;
+    out->components[0] = (int64_t)host[0];
+    out->components[1] = (int64_t)host[1];
     return LB_OK;
 }
 

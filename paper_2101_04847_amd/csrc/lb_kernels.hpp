@@ -1356,20 +1356,155 @@ k_budget_rows(const double *__restrict__ fld, int nx, int ny, int trim, BudgetCo
     }
 }
 
-// out[0..BUDGET_NQ) = part[][q] summed over the nb bands in a fixed order.
+// out[q] = sum over rows r < nr of part[r][q], q < NQV, in a fixed order.
+template <int NQV>
 __global__ void __launch_bounds__(RED_THREADS)
-k_budget_final(const double *__restrict__ part, int nb, double *__restrict__ out)
+k_sum_rows(const double *__restrict__ part, int nr, double *__restrict__ out)
 {
     __shared__ double sh[RED_THREADS / 64];
-    double a[BUDGET_NQ] = {0, 0, 0, 0, 0, 0};
-    for (int y = threadIdx.x; y < nb; y += RED_THREADS) {
+    double a[NQV];
 #pragma unroll
-        for (int q = 0; q < BUDGET_NQ; ++q) a[q] += part[(int64_t)y * RED_NQ + q];
+    for (int q = 0; q < NQV; ++q) a[q] = 0.0;
+    for (int y = threadIdx.x; y < nr; y += RED_THREADS) {
+#pragma unroll
+        for (int q = 0; q < NQV; ++q) a[q] += part[(int64_t)y * RED_NQ + q];
     }
 #pragma unroll
-    for (int q = 0; q < BUDGET_NQ; ++q) {
+    for (int q = 0; q < NQV; ++q) {
         const double r = block_combine<false>(a[q], sh);
         if (threadIdx.x == 0) out[q] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Interface phi = rho_A - rho_B = 0 (Sec. 3, Eq. 20-21): crossings of the
+// lattice lines in four directions, for the Cauchy-Crofton length.  A
+// crossing is a pair of neighbouring sites with phi > 0 at exactly one of
+// them; pairs count when both sites lie in D (rows [trim, ny - trim)), x is
+// periodic.  Row r = y - trim of part holds the pairs (x, y)-(x+1, y),
+// (x, y)-(x, y+1), (x, y)-(x+1, y+1) and (x+1, y)-(x, y+1) as integers in
+// doubles (exact below 2^53).
+constexpr int IFACE_NQ = 4;
+
+__global__ void __launch_bounds__(RED_THREADS)
+k_interface_rows(const double *__restrict__ fld, int nx, int ny, int trim, double *__restrict__ part)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    const int y = trim + blockIdx.x;
+    const int64_t n = (int64_t)nx * ny;
+    const double *rA = fld, *rB = fld + n;
+    auto pos = [&](int yy, int xx) {
+        const int64_t k = (int64_t)yy * nx + xx;
+        return rA[k] - rB[k] > 0.0;
+    };
+    const bool next = y + 1 < ny - trim;
+    double a[IFACE_NQ] = {0, 0, 0, 0};
+    for (int x = threadIdx.x; x < nx; x += RED_THREADS) {
+        const int xp = (x + 1 == nx) ? 0 : x + 1;
+        const bool p00 = pos(y, x), p10 = pos(y, xp);
+        a[0] += (p00 != p10) ? 1.0 : 0.0;
+        if (next) {
+            const bool p01 = pos(y + 1, x), p11 = pos(y + 1, xp);
+            a[1] += (p00 != p01) ? 1.0 : 0.0;
+            a[2] += (p00 != p11) ? 1.0 : 0.0;
+            a[3] += (p10 != p01) ? 1.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < IFACE_NQ; ++q) {
+        const double r = block_combine<false>(a[q], sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * RED_NQ + q] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Connected components of the two phases (Sec. 3, the topology change of the
+// interface): the A-rich set phi > 0 and its complement inside D, sites
+// joined to their row and column neighbours of the same phase (x periodic).
+// Sites of D are numbered s = (y - trim) nx + x.  Union-find on parent[]:
+// every root points to itself and every other entry to a smaller index.
+// k_cc_hook joins the two ends of each same-phase edge by a compare-and-swap
+// that re-parents a root only while it is still a root, so concurrent joins
+// lose no link and one pass over the edges suffices.
+
+__device__ __forceinline__ int cc_find(const int *parent, int a)
+{
+    int p;
+    while ((p = __hip_atomic_load(parent + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != a) a = p;
+    return a;
+}
+
+__device__ __forceinline__ bool cc_phase(const double *rA, const double *rB, int64_t k) { return rA[k] - rB[k] > 0.0; }
+
+__global__ void k_cc_init(int *__restrict__ parent, int64_t nsites)
+{
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nsites; s += (int64_t)gridDim.x * blockDim.x)
+        parent[s] = (int)s;
+}
+
+__global__ void k_cc_hook(const double *__restrict__ fld, int nx, int ny, int trim, int *parent)
+{
+    const int64_t n = (int64_t)nx * ny;
+    const double *rA = fld, *rB = fld + n;
+    const int nD = ny - 2 * trim;
+    const int64_t nsites = (int64_t)nD * nx;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nsites; s += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(s / nx), x = (int)(s % nx);
+        const int64_t k = (int64_t)(r + trim) * nx + x;
+        const bool ph = cc_phase(rA, rB, k);
+        int nb[2];
+        int cnt = 0;
+        const int xr = (x + 1 == nx) ? 0 : x + 1;
+        if (cc_phase(rA, rB, (int64_t)(r + trim) * nx + xr) == ph) nb[cnt++] = r * nx + xr;
+        if (r + 1 < nD && cc_phase(rA, rB, k + nx) == ph) nb[cnt++] = (r + 1) * nx + x;
+        for (int e = 0; e < cnt; ++e) {
+            int a = (int)s, b = nb[e];
+            while (true) {
+                a = cc_find(parent, a);
+                b = cc_find(parent, b);
+                if (a == b) break;
+                if (a < b) {
+                    const int t = a;
+                    a = b;
+                    b = t;
+                }
+                // hook root a under b if a is still a root
+                int expected = a;
+                if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT))
+                    break;
+            }
+        }
+    }
+}
+
+// Per row r of D: part[r][0] roots of phase A, [1] roots of phase B, [2]
+// same-phase edges whose ends have different roots (0 when the union is
+// complete).
+__global__ void __launch_bounds__(RED_THREADS)
+k_cc_rows(const double *__restrict__ fld, int nx, int ny, int trim, const int *__restrict__ parent,
+          double *__restrict__ part)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    const int64_t n = (int64_t)nx * ny;
+    const double *rA = fld, *rB = fld + n;
+    const int nD = ny - 2 * trim;
+    const int r = blockIdx.x;
+    double a[3] = {0, 0, 0};
+    for (int x = threadIdx.x; x < nx; x += RED_THREADS) {
+        const int s = r * nx + x;
+        const int64_t k = (int64_t)(r + trim) * nx + x;
+        const bool ph = cc_phase(rA, rB, k);
+        if (parent[s] == s) a[ph ? 0 : 1] += 1.0;
+        const int root = cc_find(parent, s);
+        const int xr = (x + 1 == nx) ? 0 : x + 1;
+        if (cc_phase(rA, rB, (int64_t)(r + trim) * nx + xr) == ph && cc_find(parent, r * nx + xr) != root) a[2] += 1.0;
+        if (r + 1 < nD && cc_phase(rA, rB, k + nx) == ph && cc_find(parent, s + nx) != root) a[2] += 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double v = block_combine<false>(a[q], sh);
+        if (threadIdx.x == 0) part[(int64_t)r * RED_NQ + q] = v;
     }
 }
 

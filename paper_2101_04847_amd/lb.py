@@ -62,6 +62,14 @@ class LbBudget(ctypes.Structure):
                 ("buoyancy", ctypes.c_double)]
 
 
+class LbInterface(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("crossings", ctypes.c_int64 * 4), ("length", ctypes.c_double)]
+
+
+class LbTopology(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("components", ctypes.c_int64 * 2)]
+
+
 _h = ctypes.c_void_p
 _lib.lb_workspace_bytes.argtypes = [ctypes.POINTER(LbConfig)]
 _lib.lb_workspace_bytes.restype = ctypes.c_size_t
@@ -76,6 +84,10 @@ _lib.lb_diagnostics.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbDiag), _dp]
 _lib.lb_diagnostics.restype = ctypes.c_int32
 _lib.lb_energy_budget.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbBudget)]
 _lib.lb_energy_budget.restype = ctypes.c_int32
+_lib.lb_interface_length.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbInterface)]
+_lib.lb_interface_length.restype = ctypes.c_int32
+_lib.lb_components.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbTopology)]
+_lib.lb_components.restype = ctypes.c_int32
 _lib.lb_get_populations.argtypes = [_h, ctypes.c_int32, ctypes.c_void_p]
 _lib.lb_get_populations.restype = ctypes.c_int32
 _lib.lb_set_populations.argtypes = [_h, ctypes.c_int32, ctypes.c_void_p]
@@ -94,6 +106,7 @@ _lib.lb_last_error.argtypes = []
 _lib.lb_last_error.restype = ctypes.c_char_p
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_energy_budget",
+           "lb_interface_length", "lb_components",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
            "lb_steps_per_pass", "lb_storage_scale", "lb_destroy", "lb_last_error")
 
@@ -257,6 +270,21 @@ class Lattice:
         b = LbBudget()
         _check(_lib.lb_energy_budget(self._h, m, ctypes.byref(b)), "lb_energy_budget")
         return {k: getattr(b, k) for k, _ in LbBudget._fields_}
+
+    def interface_length(self, m: int = 0) -> dict:
+        """Interface crossings n0, n90, n45, n135 and Cauchy-Crofton length
+        of phi = 0 inside the trimmed domain (lb_interface)."""
+        r = LbInterface()
+        _check(_lib.lb_interface_length(self._h, m, ctypes.byref(r)), "lb_interface_length")
+        c = list(r.crossings)
+        return {"t": r.t, "n0": c[0], "n90": c[1], "n45": c[2], "n135": c[3], "length": r.length}
+
+    def components(self, m: int = 0) -> dict:
+        """Connected components of phi > 0 ("A") and phi <= 0 ("B") inside
+        the trimmed domain (lb_topology)."""
+        r = LbTopology()
+        _check(_lib.lb_components(self._h, m, ctypes.byref(r)), "lb_components")
+        return {"t": r.t, "A": r.components[0], "B": r.components[1]}
 
     def get_populations(self, m: int = 0):
         import torch

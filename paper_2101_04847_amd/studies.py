@@ -9,8 +9,9 @@ library's outputs only; every lattice update runs in the HIP kernels).
   drift, mixing-width error and final density error against FP64.
 * ensemble_statistics: the 16-member ensemble (FP32) for 20000 steps with
   averages every 100 steps; ensemble mean and spread of the mixing width,
-  kinetic and potential energy, buoyancy flux and viscous term (Eq. 15-22),
-  per coupling.
+  kinetic and potential energy and every term of the kinetic-energy balance
+  (Eq. 15-22: bulk pressure, Korteweg and tau stresses, viscous term,
+  buoyancy), per coupling, and how well Eq. 17 closes per member.
 """
 from __future__ import annotations
 
@@ -49,12 +50,6 @@ def phi_reference(profile0, trim=TRIM):
     return 0.5 * abs(p[len(p) - trim - 1] - p[trim])
 
 
-def viscous_term(d, nx, ny, tau):
-    """-eta <omega^2> of Eq. 22 with eta = mean density * c_s^2 (tau - 1/2)."""
-    rho_bar = (d["mass_A"] + d["mass_B"]) / (nx * ny)
-    return -rho_bar * (tau - 0.5) / 3.0 * d["omega2"]
-
-
 def fp32_vs_fp64_large(lb, inputs, stream, log, steps=2000):
     wl = inputs.LARGE_10000x5000
     fields = {}
@@ -82,11 +77,14 @@ def fp32_vs_fp64_large(lb, inputs, stream, log, steps=2000):
     }
 
 
-def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0)):
+BUDGET_KEYS = ("pb", "korteweg", "ktau", "viscous")
+
+
+def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0), budget=False):
     lat = _lattice(lb, wls, storage, stream, rho0)
     n = len(wls)
-    out = [{"t": [], "mass_A": [], "mass_B": [], "Ek": [], "Ep": [], "buoyancy": [], "omega2": [], "h": []}
-           for _ in range(n)]
+    keys = ["t", "mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "h"] + (list(BUDGET_KEYS) if budget else [])
+    out = [{k: [] for k in keys} for _ in range(n)]
     phi_refs = []
     for m in range(n):
         d = lat.diagnostics(m, profile=True)
@@ -102,6 +100,10 @@ def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0)):
             for k in ("mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2"):
                 s[k].append(d[k])
             s["h"].append(lb.mixing_width(d["phi_profile"], phi_refs[m], TRIM))
+            if budget:
+                b = lat.energy_budget(m)
+                for k in BUDGET_KEYS:
+                    s[k].append(b[k])
         if t and t % (steps // 4) == 0:
             log(f"{tag}: t = {t} ({time.perf_counter() - t0:.1f} s)")
     final = []
@@ -148,31 +150,37 @@ def reduced_precision(lb, inputs, stream, log, steps=20000, every=100):
 def ensemble_statistics(lb, inputs, stream, log, steps=20000, every=100):
     wls = inputs.ensemble_16()
     t0 = time.perf_counter()
-    ser, _ = _series(lb, wls, lb.F32, stream, steps, every, log, "ensemble f32")
+    ser, _ = _series(lb, wls, lb.F32, stream, steps, every, log, "ensemble f32", budget=True)
     wall = time.perf_counter() - t0
     out = {"steps": steps, "every": every, "members": len(wls), "wall_s": round(wall, 1), "groups": {}}
     sample = list(range(0, steps + 1, steps // 10))
     for G in (0.5, 1.5):
         idx = [k for k, wl in enumerate(wls) if wl.G == G]
         grp = {}
-        for key in ("h", "Ek", "Ep", "buoyancy"):
+        for key in ("h", "Ek", "Ep", "buoyancy") + BUDGET_KEYS:
             a = np.array([ser[k][key] for k in idx])
             grp[key] = {"t": sample,
                         "mean": [float(a[:, t // every].mean()) for t in sample],
                         "std": [float(a[:, t // every].std()) for t in sample]}
-        visc = np.array([[viscous_term({"mass_A": ser[k]["mass_A"][j], "mass_B": ser[k]["mass_B"][j],
-                                         "omega2": ser[k]["omega2"][j]}, wls[k].nx, wls[k].ny, wls[k].tau)
-                          for j in range(len(ser[k]["t"]))] for k in idx])
-        grp["viscous"] = {"t": sample, "mean": [float(visc[:, t // every].mean()) for t in sample],
-                          "std": [float(visc[:, t // every].std()) for t in sample]}
-        # energy budget of Eq. 17 without the pressure-work term: residual
-        # d(E_k + E_p)/dt - viscous, averaged over the second half of the run
-        res = []
-        for j, k in enumerate(idx):
-            ek, ep = np.array(ser[k]["Ek"]), np.array(ser[k]["Ep"])
-            dE = np.gradient(ek + ep, every)
-            res.append(float(np.mean((dE - visc[j])[len(dE) // 2:])))
-        grp["budget_residual_mean"] = float(np.mean(res))
+        # Eq. 17 over the second half of the run: the change of E_k against
+        # the trapezoid integral of -(pb + korteweg + ktau) + viscous -
+        # buoyancy (samples every `every` steps), relative to the summed
+        # magnitudes of the integrated terms
+        res, parts = [], []
+        for k in idx:
+            s = ser[k]
+            t = np.array(s["t"], dtype=np.float64)
+            h0 = len(t) // 2
+            rhs = np.array([[-s["pb"][j], -s["korteweg"][j], -s["ktau"][j], s["viscous"][j], -s["buoyancy"][j]]
+                            for j in range(len(t))])
+            integ = np.trapezoid(rhs[h0:], t[h0:], axis=0)
+            d_ek = s["Ek"][-1] - s["Ek"][h0]
+            res.append(float(abs(d_ek - integ.sum()) / np.sum(np.abs(integ))))
+            parts.append(integ)
+        grp["balance_residual_rel"] = {"mean": float(np.mean(res)), "max": float(np.max(res))}
+        pm = np.mean(np.array(parts), axis=0)
+        grp["balance_integrals_second_half"] = dict(zip(("-pb", "-korteweg", "-ktau", "viscous", "-buoyancy"),
+                                                        [float(v) for v in pm]))
         grp["members"] = len(idx)
         out["groups"][f"G={G}"] = grp
     return out

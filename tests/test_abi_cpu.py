@@ -45,6 +45,8 @@ def test_header_constants_match_binding(lb):
     assert ctypes.sizeof(lb.LbDiag) == 8 + 16 + 5 * 8 + 8
     assert ctypes.sizeof(lb.LbConfig) == 4 + 4 + 8 + 8 * 4
     assert ctypes.sizeof(lb.LbBudget) == 8 + 6 * 8
+    assert ctypes.sizeof(lb.LbInterface) == 8 + 4 * 8 + 8
+    assert ctypes.sizeof(lb.LbTopology) == 8 + 2 * 8
 
 
 def _member(lb, nx=32, ny=30, **kw):
@@ -125,6 +127,10 @@ def test_unknown_handle_is_rejected(lb):
     assert lb._lib.lb_diagnostics(bogus, 0, ctypes.byref(d), None) == lb.LB_ESTATE
     b = lb.LbBudget()
     assert lb._lib.lb_energy_budget(bogus, 0, ctypes.byref(b)) == lb.LB_ESTATE
+    r = lb.LbInterface()
+    assert lb._lib.lb_interface_length(bogus, 0, ctypes.byref(r)) == lb.LB_ESTATE
+    tp = lb.LbTopology()
+    assert lb._lib.lb_components(bogus, 0, ctypes.byref(tp)) == lb.LB_ESTATE
     assert lb._lib.lb_fields(bogus, 0, None, None, None, None) == lb.LB_ESTATE
     assert "live" in lb.last_error()
 
@@ -138,3 +144,15 @@ def test_oracle_is_not_imported_by_the_product(lb):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "orc_" not in text, fn
+
+
+@pytest.mark.parametrize("lang", ["c", "c++"])
+def test_header_compiles_cleanly(lang, tmp_path):
+    """include/lb.h is self-contained and warning-free as C and C++."""
+    import subprocess
+    src = tmp_path / ("t.c" if lang == "c" else "t.cpp")
+    src.write_text('#include "lb.h"\nint main(void) { return (int)sizeof(lb_config); }\n')
+    cc = "gcc" if lang == "c" else "g++"
+    r = subprocess.run([cc, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"),
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr

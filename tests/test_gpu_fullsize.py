@@ -28,6 +28,7 @@ def test_production_size_three_steps():
     fg = lat.fields(0)
     fg = {k: v.cpu().numpy() for k, v in fg.items()}
     dg = lat.diagnostics(0)
+    ig = lat.interface_length(0)
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -42,5 +43,9 @@ def test_production_size_three_steps():
         err = np.max(np.abs(fg[k] - mo[k])) / np.max(np.abs(mo[k]))
         print(f"[case] {k} max rel err {err:.3e}", flush=True)
         assert err <= 1e-12, k
+    from oracle import interface
+    io = interface.interface_length(mo["rhoA"], mo["rhoB"], 10)
+    for k in ("n0", "n90", "n45", "n135", "length"):
+        assert ig[k] == io[k], k
     assert dg["mass_A"] == pytest.approx(do["mass_A"], rel=1e-12)
     assert dg["Ek"] == pytest.approx(do["Ek"], rel=1e-12)

