@@ -194,7 +194,7 @@ def main() -> int:
     d = lat.diagnostics(0)
     # cost of the analysis passes (each call synchronises): energy-budget
     # averages and the kinetic-energy balance terms, best of three
-    t_diag, t_budget = [], []
+    t_diag, t_budget, t_iface, t_comp = [], [], [], []
     for _ in range(3):
         t0 = time.perf_counter()
         lat.diagnostics(0)
@@ -202,6 +202,12 @@ def main() -> int:
         t0 = time.perf_counter()
         budget = lat.energy_budget(0)
         t_budget.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        iface = lat.interface_length(0)
+        t_iface.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        comps = lat.components(0)
+        t_comp.append(time.perf_counter() - t0)
     release(lat)
     sites = wl.nx * wl.ny
     mlups = sites / (ms_step / 1e3) / 1e6
@@ -234,7 +240,10 @@ def main() -> int:
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
         "analysis_ms": {"diagnostics": round(min(t_diag) * 1e3, 3), "energy_budget": round(min(t_budget) * 1e3, 3),
-                        "budget": {k: budget[k] for k in ("pb", "korteweg", "ktau", "viscous", "buoyancy")}},
+                        "interface_length": round(min(t_iface) * 1e3, 3), "components": round(min(t_comp) * 1e3, 3),
+                        "budget": {k: budget[k] for k in ("pb", "korteweg", "ktau", "viscous", "buoyancy")},
+                        "interface": {"length": iface["length"], "components_A": comps["A"],
+                                      "components_B": comps["B"]}},
     }
     if not args.no_extras:
         if spp == 2:

@@ -835,6 +835,7 @@ int32_t lb_components(lb_handle *h, int32_t m, lb_topology *out)
     hipLaunchKernelGGL(k_cc_init, dim3(grid), dim3(256), 0, h->stream, parent, nsites);
     hipLaunchKernelGGL(k_cc_hook, dim3(grid), dim3(256), 0, h->stream, (const double *)fld, M.nx, M.ny,
                        h->cfg.diag_trim, parent);
+    hipLaunchKernelGGL(k_cc_compress, dim3(grid), dim3(256), 0, h->stream, parent, nsites);
     hipLaunchKernelGGL(k_cc_rows, dim3(nD), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
                        h->cfg.diag_trim, (const int *)parent, part);
     hipLaunchKernelGGL(k_sum_rows<3>, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, nD, red);

@@ -1425,13 +1425,32 @@ k_interface_rows(const double *__restrict__ fld, int nx, int ny, int trim, doubl
 // every root points to itself and every other entry to a smaller index.
 // k_cc_hook joins the two ends of each same-phase edge by a compare-and-swap
 // that re-parents a root only while it is still a root, so concurrent joins
-// lose no link and one pass over the edges suffices.
+// lose no link and one pass over the edges suffices.  Finds halve the path
+// they walk (a non-root entry may always be replaced by its grandparent: an
+// ancestor in the same tree with a smaller index), which keeps the trees
+// shallow; k_cc_compress then points every entry at its root.
+
+__device__ __forceinline__ int cc_load(const int *parent, int a)
+{
+    return __hip_atomic_load(parent + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ int cc_find(const int *parent, int a)
 {
     int p;
-    while ((p = __hip_atomic_load(parent + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != a) a = p;
+    while ((p = cc_load(parent, a)) != a) a = p;
     return a;
+}
+
+__device__ __forceinline__ int cc_find_halve(int *parent, int a)
+{
+    while (true) {
+        const int p = cc_load(parent, a);
+        if (p == a) return a;
+        const int gp = cc_load(parent, p);
+        if (gp != p) __hip_atomic_store(parent + a, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a = gp;
+    }
 }
 
 __device__ __forceinline__ bool cc_phase(const double *rA, const double *rB, int64_t k) { return rA[k] - rB[k] > 0.0; }
@@ -1460,8 +1479,8 @@ __global__ void k_cc_hook(const double *__restrict__ fld, int nx, int ny, int tr
         for (int e = 0; e < cnt; ++e) {
             int a = (int)s, b = nb[e];
             while (true) {
-                a = cc_find(parent, a);
-                b = cc_find(parent, b);
+                a = cc_find_halve(parent, a);
+                b = cc_find_halve(parent, b);
                 if (a == b) break;
                 if (a < b) {
                     const int t = a;
@@ -1475,6 +1494,14 @@ __global__ void k_cc_hook(const double *__restrict__ fld, int nx, int ny, int tr
                     break;
             }
         }
+    }
+}
+
+__global__ void k_cc_compress(int *parent, int64_t nsites)
+{
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nsites; s += (int64_t)gridDim.x * blockDim.x) {
+        const int r = cc_find_halve(parent, (int)s);
+        __hip_atomic_store(parent + s, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

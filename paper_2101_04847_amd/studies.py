@@ -11,7 +11,13 @@ library's outputs only; every lattice update runs in the HIP kernels).
   averages every 100 steps; ensemble mean and spread of the mixing width,
   kinetic and potential energy and every term of the kinetic-energy balance
   (Eq. 15-22: bulk pressure, Korteweg and tau stresses, viscous term,
-  buoyancy), per coupling, and how well Eq. 17 closes per member.
+  buoyancy), per coupling, and how well Eq. 17 closes per member; the
+  interface length and the phase component counts, and a fit of the Korteweg
+  flux against the rate of change of interface length (Eq. 21).
+* surface_tension: at G = 1.5, tau = 1, the Korteweg part of the surface
+  tension kappa int (dphi/dy)^2 dy of a relaxed flat interface and the full
+  surface tension from Laplace's law on static drops (Eq. 12 pressure), the
+  references for the Eq. 21 fit.
 """
 from __future__ import annotations
 
@@ -83,7 +89,9 @@ BUDGET_KEYS = ("pb", "korteweg", "ktau", "viscous")
 def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0), budget=False):
     lat = _lattice(lb, wls, storage, stream, rho0)
     n = len(wls)
-    keys = ["t", "mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "h"] + (list(BUDGET_KEYS) if budget else [])
+    keys = ["t", "mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "h"]
+    if budget:
+        keys += list(BUDGET_KEYS) + ["length", "comp_A", "comp_B"]
     out = [{k: [] for k in keys} for _ in range(n)]
     phi_refs = []
     for m in range(n):
@@ -104,6 +112,10 @@ def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0), b
                 b = lat.energy_budget(m)
                 for k in BUDGET_KEYS:
                     s[k].append(b[k])
+                s["length"].append(lat.interface_length(m)["length"])
+                c = lat.components(m)
+                s["comp_A"].append(c["A"])
+                s["comp_B"].append(c["B"])
         if t and t % (steps // 4) == 0:
             log(f"{tag}: t = {t} ({time.perf_counter() - t0:.1f} s)")
     final = []
@@ -157,7 +169,7 @@ def ensemble_statistics(lb, inputs, stream, log, steps=20000, every=100):
     for G in (0.5, 1.5):
         idx = [k for k, wl in enumerate(wls) if wl.G == G]
         grp = {}
-        for key in ("h", "Ek", "Ep", "buoyancy") + BUDGET_KEYS:
+        for key in ("h", "Ek", "Ep", "buoyancy") + BUDGET_KEYS + ("length", "comp_A", "comp_B"):
             a = np.array([ser[k][key] for k in idx])
             grp[key] = {"t": sample,
                         "mean": [float(a[:, t // every].mean()) for t in sample],
@@ -181,8 +193,76 @@ def ensemble_statistics(lb, inputs, stream, log, steps=20000, every=100):
         pm = np.mean(np.array(parts), axis=0)
         grp["balance_integrals_second_half"] = dict(zip(("-pb", "-korteweg", "-ktau", "viscous", "-buoyancy"),
                                                         [float(v) for v in pm]))
+        # Eq. 21: <u . div P^K> against (1/D) dL/dt (centred differences of
+        # the length series); least-squares slope = effective surface tension
+        # and the correlation of the two series, per member, after the first
+        # tenth of the run
+        fits = []
+        for k in idx:
+            s = ser[k]
+            t = np.array(s["t"], dtype=np.float64)
+            area = wls[k].nx * (wls[k].ny - 2 * TRIM)
+            dl = np.gradient(np.array(s["length"]), t) / area
+            kf = np.array(s["korteweg"])
+            sel = t >= steps // 10
+            x, y = dl[sel], kf[sel]
+            slope = float(np.dot(x, y) / max(np.dot(x, x), 1e-300))
+            corr = float(np.corrcoef(x, y)[0, 1]) if np.std(x) > 0 and np.std(y) > 0 else float("nan")
+            fits.append((slope, corr))
+        grp["eq21_gamma_fit"] = {"mean": float(np.mean([f[0] for f in fits])),
+                                 "per_member": [round(f[0], 5) for f in fits]}
+        grp["eq21_correlation"] = {"mean": float(np.mean([f[1] for f in fits])),
+                                   "per_member": [round(f[1], 3) for f in fits]}
         grp["members"] = len(idx)
         out["groups"][f"G={G}"] = grp
+    return out
+
+
+def surface_tension(lb, stream, log, G=1.5, tau=1.0, steps=20000):
+    """Korteweg surface tension of a flat interface and Laplace surface
+    tension of static drops at (G, tau), from relaxed lattice states."""
+    cs2 = 1.0 / 3.0
+    kappa = cs2 * cs2 * G / 4.0
+    out = {"G": G, "tau": tau, "steps": steps}
+    # flat: periodic in y, the A-rich slab in the middle half (two interfaces)
+    nx, ny = 16, 256
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    s_ = 0.5 * (np.tanh((y - ny / 4) / 1.5) - np.tanh((y - 3 * ny / 4) / 1.5))
+    rA, rB = 0.05 + 1.0 * s_, 0.05 + 1.0 * (1 - s_)
+    lat = lb.Lattice([lb.Member(nx, ny, rA, rB, tau=(tau, tau), G=G)], bc_y=lb.PERIODIC_Y, stream=stream,
+                     graph_chunk=100, diag_trim=2)
+    lat.step(steps)
+    f = lat.fields(0)
+    phi = (f["rhoA"] - f["rhoB"]).cpu().numpy().mean(axis=1)
+    _close(lat)
+    dphi = 0.5 * (np.roll(phi, -1) - np.roll(phi, 1))
+    out["gamma_korteweg"] = float(kappa * np.sum(dphi * dphi) / 2.0)
+    # drops in a periodic box: Laplace's law dp = sigma / R
+    n = 256
+    radii, dps = [], []
+    for R in (24.0, 32.0, 48.0):
+        x = np.arange(n)[None, :] - n / 2 + 0.5
+        yy = np.arange(n)[:, None] - n / 2 + 0.5
+        s_ = 0.5 * (1 - np.tanh((np.hypot(x, yy) - R) / 1.5))
+        rA, rB = 0.05 + 1.0 * s_, 0.05 + 1.0 * (1 - s_)
+        lat = lb.Lattice([lb.Member(n, n, rA, rB, tau=(tau, tau), G=G)], bc_y=lb.PERIODIC_Y, stream=stream,
+                         graph_chunk=100, diag_trim=2)
+        lat.step(steps)
+        f = {k: v.cpu().numpy() for k, v in lat.fields(0).items()}
+        _close(lat)
+        p = cs2 * (f["rhoA"] + f["rhoB"]) + G * cs2 * f["rhoA"] * f["rhoB"]   # Eq. 12
+        c = n // 2
+        p_in = p[c - 3:c + 3, c - 3:c + 3].mean()
+        p_out = np.concatenate([p[:6, :].ravel(), p[-6:, :].ravel()]).mean()
+        # radius of the relaxed drop from its area
+        radii.append(float(np.sqrt(np.count_nonzero(f["rhoA"] > f["rhoB"]) / np.pi)))
+        dps.append(float(p_in - p_out))
+        log(f"surface tension: drop R = {radii[-1]:.2f}: dp = {dps[-1]:.4e}")
+    inv = 1.0 / np.array(radii)
+    sigma, icpt = np.polyfit(inv, np.array(dps), 1)
+    out["sigma_laplace"] = float(sigma)
+    out["laplace_intercept"] = float(icpt)
+    out["drops"] = {"R": radii, "dp": dps}
     return out
 
 
@@ -194,4 +274,6 @@ def run_all(lb, inputs, stream, log):
     rep["reduced_precision"] = reduced_precision(lb, inputs, stream, log)
     log("study: 16-member ensemble statistics")
     rep["ensemble_statistics"] = ensemble_statistics(lb, inputs, stream, log)
+    log("study: surface tension at G = 1.5, tau = 1")
+    rep["surface_tension"] = surface_tension(lb, stream, log)
     return rep
