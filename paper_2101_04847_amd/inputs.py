@@ -67,6 +67,26 @@ def multi_mode(nx: int, ny: int, seed: int, n_modes: int = 32, amp_max: float = 
     return two_phase_densities(nx, ny, interface_height(nx, ny, amps, phases), **kw)
 
 
+def white_noise_height(nx: int, ny: int, seed: int, amplitude: float = 4.0) -> np.ndarray:
+    """Interface height (ny - 1)/2 + amplitude * xi(x) with xi ~ U[-1, 1]
+    independent per column (the paper's white-noise deformation of
+    amplitude 4 grid points), seeded."""
+    rng = np.random.default_rng(seed)
+    return 0.5 * (ny - 1) + float(amplitude) * rng.uniform(-1.0, 1.0, nx)
+
+
+def profile_densities(nx: int, ny: int, height: np.ndarray, y_prof: np.ndarray, rho_a_prof: np.ndarray,
+                      rho_b_prof: np.ndarray):
+    """Densities [ny][nx] that follow a given one-dimensional interface
+    profile (values at offsets y_prof from the interface, increasing) shifted
+    to height(x) in every column (linear interpolation, constant beyond the
+    ends of the profile)."""
+    y = np.arange(ny, dtype=np.float64)[:, None] - height[None, :]
+    rho_a = np.interp(y.ravel(), y_prof, rho_a_prof).reshape(ny, nx)
+    rho_b = np.interp(y.ravel(), y_prof, rho_b_prof).reshape(ny, nx)
+    return np.ascontiguousarray(rho_a), np.ascontiguousarray(rho_b)
+
+
 @dataclass
 class Workload:
     """One realisation: grid, coupling, gravity and the seed of its interface."""

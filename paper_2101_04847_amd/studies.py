@@ -14,6 +14,12 @@ library's outputs only; every lattice update runs in the HIP kernels).
   buoyancy), per coupling, and how well Eq. 17 closes per member; the
   interface length and the phase component counts, and a fit of the Korteweg
   flux against the rate of change of interface length (Eq. 21).
+* paper_runs: ensembles at the paper's own parameters (Sec. 2: 10^4 x 5 10^3,
+  tau = 0.53, g = 9e-6, bulk total density 1.10, G = 0.1381 immiscible or
+  0.0805 miscible, the equilibrium immiscible interface with a white-noise
+  deformation of amplitude 4, 90000 steps): every 1000 steps the energies,
+  all kinetic-energy balance terms, the interface length, the component
+  counts and the mixing width of every member.
 * surface_tension: at G = 1.5, tau = 1, the Korteweg part of the surface
   tension kappa int (dphi/dy)^2 dy of a relaxed flat interface and the full
   surface tension from Laplace's law on static drops (Eq. 12 pressure), the
@@ -266,6 +272,87 @@ def surface_tension(lb, stream, log, G=1.5, tau=1.0, steps=20000):
     return out
 
 
+PAPER = {"nx": 10000, "ny": 5000, "tau": 0.53, "g": 9e-6, "rho_total": 1.10, "steps": 90000,
+         "G": {"immiscible": 0.1381, "miscible": 0.0805}}
+
+
+def equilibrium_profile(lb, stream, log, G=0.1381, tau=0.53, rho_total=1.10, steps=30000):
+    """The relaxed flat interface of the immiscible model (Sec. 2): a column
+    periodic in y with an A-rich slab in its middle half, relaxed for `steps`
+    steps; returns the offsets from the lower interface (B-rich below, A-rich
+    above) and the row-mean densities there, and the bulk values."""
+    nx, ny = 8, 512
+    y = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    s_ = 0.5 * (np.tanh((y - ny / 4) / 1.5) - np.tanh((y - 3 * ny / 4) / 1.5))
+    maj, mnr = rho_total / 1.1, rho_total * 0.1 / 1.1
+    rA = mnr + (maj - mnr) * s_
+    rB = mnr + (maj - mnr) * (1.0 - s_)
+    lat = lb.Lattice([lb.Member(nx, ny, rA, rB, tau=(tau, tau), G=G)], bc_y=lb.PERIODIC_Y, stream=stream,
+                     graph_chunk=100, diag_trim=2)
+    lat.step(steps)
+    f = {k: v.cpu().numpy().mean(axis=1) for k, v in lat.fields(0).items()}
+    _close(lat)
+    phi = f["rhoA"] - f["rhoB"]
+    lo = ny // 4 - 60
+    j = lo + int(np.argmax(phi[lo:ny // 2] > 0.0))          # first row above the lower interface
+    yc = (j - 1) + (-phi[j - 1]) / (phi[j] - phi[j - 1])     # phi = 0 by linear interpolation
+    rows = np.arange(ny // 4 - 60, ny // 4 + 60)
+    prof = {"y": (rows - yc).tolist(), "rhoA": f["rhoA"][rows].tolist(), "rhoB": f["rhoB"][rows].tolist(),
+            "bulk_A_phase": [float(f["rhoA"][ny // 2]), float(f["rhoB"][ny // 2])],
+            "bulk_B_phase": [float(f["rhoA"][0]), float(f["rhoB"][0])]}
+    log(f"equilibrium profile: A phase (rho_A, rho_B) = {prof['bulk_A_phase']}, "
+        f"B phase = {prof['bulk_B_phase']}")
+    return prof
+
+
+def paper_runs(lb, inputs, stream, log, case="immiscible", members=5, seed0=0, storage=None, steps=None,
+               every=1000):
+    """Ensemble at the paper's parameters (module doc); returns the series."""
+    P = PAPER
+    steps = P["steps"] if steps is None else steps
+    storage = lb.F32 if storage is None else storage
+    G = P["G"][case]
+    prof = equilibrium_profile(lb, stream, log, tau=P["tau"], rho_total=P["rho_total"])
+    yp, pa, pb = (np.array(prof[k]) for k in ("y", "rhoA", "rhoB"))
+    mem = []
+    for k in range(members):
+        h = inputs.white_noise_height(P["nx"], P["ny"], seed0 + k, 4.0)
+        rA, rB = inputs.profile_densities(P["nx"], P["ny"], h, yp, pa, pb)
+        mem.append(lb.Member(P["nx"], P["ny"], rA, rB, tau=(P["tau"], P["tau"]), G=G,
+                             g=((0.0, -P["g"]), (0.0, P["g"]))))
+        del rA, rB
+    lat = lb.Lattice(mem, forcing=lb.FORCE_SHIFT, storage=storage, graph_chunk=100, stream=stream, diag_trim=TRIM)
+    log(f"paper runs {case}: {members} members, steps per pass {lat.steps_per_pass}, tile {lat.tile_shape(0)}")
+    keys = ("t", "Ek", "Ep", "buoyancy", "omega2", "pb", "korteweg", "ktau", "viscous", "eta", "length",
+            "comp_A", "comp_B", "h", "mass_A", "mass_B")
+    ser = [{k: [] for k in keys} for _ in range(members)]
+    phi_refs = [phi_reference(lat.diagnostics(m, profile=True)["phi_profile"]) for m in range(members)]
+    t0 = time.perf_counter()
+    for t in range(0, steps + 1, every):
+        if t:
+            lat.step(every)
+        for m in range(members):
+            d = lat.diagnostics(m, profile=True, check_finite=False)
+            b = lat.energy_budget(m)
+            il = lat.interface_length(m)
+            c = lat.components(m)
+            s = ser[m]
+            s["t"].append(t)
+            for k in ("Ek", "Ep", "buoyancy", "omega2", "mass_A", "mass_B"):
+                s[k].append(d[k])
+            for k in ("pb", "korteweg", "ktau", "viscous", "eta"):
+                s[k].append(b[k])
+            s["length"].append(il["length"])
+            s["comp_A"].append(c["A"])
+            s["comp_B"].append(c["B"])
+            s["h"].append(lb.mixing_width(d["phi_profile"], phi_refs[m], TRIM))
+        if t and t % (10 * every) == 0:
+            log(f"paper runs {case}: t = {t} ({time.perf_counter() - t0:.0f} s)")
+    _close(lat)
+    return {"case": case, "G": G, "params": P, "storage": lb.STORAGE_NAMES[storage], "seed0": seed0,
+            "every": every, "profile": prof, "wall_s": round(time.perf_counter() - t0, 1), "members": ser}
+
+
 def run_all(lb, inputs, stream, log):
     rep = {}
     log("study: FP32 vs FP64 on 10000x5000")
@@ -277,3 +364,32 @@ def run_all(lb, inputs, stream, log):
     log("study: surface tension at G = 1.5, tau = 1")
     rep["surface_tension"] = surface_tension(lb, stream, log)
     return rep
+
+
+def main(argv):
+    """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS]"""
+    import json
+    import sys as _sys
+
+    import torch
+
+    from paper_2101_04847_amd import inputs, lb
+
+    if len(argv) < 5 or argv[0] != "paper-runs":
+        raise SystemExit(main.__doc__)
+
+    def log(*a):
+        print("[study]", *a, file=_sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    steps = int(argv[5]) if len(argv) > 5 else None
+    rep = paper_runs(lb, inputs, stream, log, case=argv[1], members=int(argv[2]), seed0=int(argv[3]), steps=steps)
+    with open(argv[4], "w") as fh:
+        json.dump(rep, fh)
+    print(json.dumps({"out": argv[4], "case": rep["case"], "members": len(rep["members"]), "wall_s": rep["wall_s"]}))
+
+
+if __name__ == "__main__":
+    import sys
+    main(sys.argv[1:])
