@@ -76,19 +76,31 @@ def hbm_frac(storage, spp, ms_step, sites):
     return round(BYTES_PER_LU[storage] * sites / (ms_step * spp / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
-def time_steps(lat, steps, warmup, stream):
+def time_steps(lat, steps, warmup, stream, chunk=100, chunks_out=None):
     """ms per step over `steps` steps, timed with events on the lattice's
-    stream after `warmup` untimed steps; plus the host wall time."""
+    stream after `warmup` untimed steps; plus the host wall time.  Events
+    also bracket every `chunk` steps (one graph replay); their per-chunk
+    times go to chunks_out when given."""
     import torch
     lat.step(warmup)
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_chunks = max(1, steps // chunk)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(n_chunks + 1)]
+    ev_end = torch.cuda.Event(enable_timing=True)
     w0 = time.perf_counter()
-    ev0.record(stream)
-    lat.step(steps)
-    ev1.record(stream)
+    evs[0].record(stream)
+    done = 0
+    for k in range(n_chunks):
+        n = chunk if k < n_chunks - 1 else steps - done
+        lat.step(n)
+        done += n
+        evs[k + 1].record(stream)
+    ev_end.record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - w0
+    if chunks_out is not None:
+        chunks_out.extend(evs[k].elapsed_time(evs[k + 1]) / (chunk if k < n_chunks - 1 else steps - chunk * k)
+                          for k in range(n_chunks))
+    return evs[0].elapsed_time(ev_end) / steps, time.perf_counter() - w0
 
 
 def release(lat):
@@ -190,7 +202,8 @@ def main() -> int:
     tx, th = lat.tile_shape()
     spp = lat.steps_per_pass
     log(f"{wl.name} storage={args.storage} steps/pass={spp} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
-    ms_step, wall = time_steps(lat, args.steps, args.warmup, stream)
+    chunk_ms = []
+    ms_step, wall = time_steps(lat, args.steps, args.warmup, stream, chunks_out=chunk_ms)
     d = lat.diagnostics(0)
     # cost of the analysis passes (each call synchronises): energy-budget
     # averages and the kinetic-energy balance terms, best of three
@@ -239,6 +252,9 @@ def main() -> int:
                    "tile": [tx, th], "graph_chunk": 100, "wall_s": round(wall, 3)},
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
+        # ms per step of each 100-step graph replay inside the timed region
+        "chunk_ms_per_step": {"median": round(float(sorted(chunk_ms)[len(chunk_ms) // 2]), 4),
+                              "min": round(min(chunk_ms), 4), "max": round(max(chunk_ms), 4), "n": len(chunk_ms)},
         "analysis_ms": {"diagnostics": round(min(t_diag) * 1e3, 3), "energy_budget": round(min(t_budget) * 1e3, 3),
                         "interface_length": round(min(t_iface) * 1e3, 3), "components": round(min(t_comp) * 1e3, 3),
                         "budget": {k: budget[k] for k in ("pb", "korteweg", "ktau", "viscous", "buoyancy")},

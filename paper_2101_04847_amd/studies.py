@@ -324,7 +324,7 @@ def paper_runs(lb, inputs, stream, log, case="immiscible", members=5, seed0=0, s
     lat = lb.Lattice(mem, forcing=lb.FORCE_SHIFT, storage=storage, graph_chunk=100, stream=stream, diag_trim=TRIM)
     log(f"paper runs {case}: {members} members, steps per pass {lat.steps_per_pass}, tile {lat.tile_shape(0)}")
     keys = ("t", "Ek", "Ep", "buoyancy", "omega2", "pb", "korteweg", "ktau", "viscous", "eta", "length",
-            "comp_A", "comp_B", "h", "mass_A", "mass_B")
+            "comp_A", "comp_B", "h", "mass_A", "mass_B", "umax")
     ser = [{k: [] for k in keys} for _ in range(members)]
     phi_refs = [phi_reference(lat.diagnostics(m, profile=True)["phi_profile"]) for m in range(members)]
     t0 = time.perf_counter()
@@ -338,7 +338,7 @@ def paper_runs(lb, inputs, stream, log, case="immiscible", members=5, seed0=0, s
             c = lat.components(m)
             s = ser[m]
             s["t"].append(t)
-            for k in ("Ek", "Ep", "buoyancy", "omega2", "mass_A", "mass_B"):
+            for k in ("Ek", "Ep", "buoyancy", "omega2", "mass_A", "mass_B", "umax"):
                 s[k].append(d[k])
             for k in ("pb", "korteweg", "ktau", "viscous", "eta"):
                 s[k].append(b[k])
@@ -367,7 +367,7 @@ def run_all(lb, inputs, stream, log):
 
 
 def main(argv):
-    """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS]"""
+    """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS [STORAGE]]"""
     import json
     import sys as _sys
 
@@ -383,8 +383,10 @@ def main(argv):
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    steps = int(argv[5]) if len(argv) > 5 else None
-    rep = paper_runs(lb, inputs, stream, log, case=argv[1], members=int(argv[2]), seed0=int(argv[3]), steps=steps)
+    steps = int(argv[5]) if len(argv) > 5 and int(argv[5]) > 0 else None
+    storage = {"f64": lb.F64, "f32": lb.F32}[argv[6]] if len(argv) > 6 else None
+    rep = paper_runs(lb, inputs, stream, log, case=argv[1], members=int(argv[2]), seed0=int(argv[3]), steps=steps,
+                     storage=storage)
     with open(argv[4], "w") as fh:
         json.dump(rep, fh)
     print(json.dumps({"out": argv[4], "case": rep["case"], "members": len(rep["members"]), "wall_s": rep["wall_s"]}))
