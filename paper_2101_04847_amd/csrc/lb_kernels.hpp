@@ -1,30 +1,40 @@
-// gfx950 kernels of the two-component D2Q9 Shan-Chen lattice Boltzmann step.
+// gfx950 kernels of the two-component D2Q9 Shan-Chen lattice Boltzmann step
+// and of the analysis of its fields.
 //
 // Method (paper Sec. 2): per component s, rho_s = sum_i f_i^s (Eq. 1);
 // Shan-Chen force F_s = -G rho_s sum_i w_i rho_sbar(x + c_i) c_i (Eq. 5) plus
-// buoyancy rho_s g_s (Eq. 7); common velocity weighted by 1/tau_s (Eq. 1);
-// BGK relaxation towards f^eq(rho_s, u + tau_s F_s / rho_s) (Eq. 2-3) or Guo
-// forcing; streaming with periodic x and halfway bounce-back walls.
+// buoyancy rho_s g_s (Eq. 7), i.e. rho_s a_s with the acceleration
+// a_s = -G sum_i w_i rho_sbar(x + c_i) c_i + g_s; common velocity weighted by
+// 1/tau_s (Eq. 1); BGK relaxation towards f^eq(rho_s, u + tau_s a_s)
+// (Eq. 2-3) or Guo forcing; streaming with periodic x and halfway
+// bounce-back walls.
 //
-// Storage: buffer[s][i][y][pitch] per member, x fastest, pitch a multiple of
-// 64 elements.  A buffer holds post-collision populations f*(t-1); the
+// Storage: per member two buffers of row blocks [y][s][i][pitch] (the 18
+// row segments of one lattice row adjacent, x fastest, pitch a multiple of
+// 64 elements).  A buffer holds post-collision populations f*(t-1); the
 // pre-collision state f(t) is obtained by PULLING: f_i(x) = f*_i(x - c_i),
 // or f*_opp(i)(x) where x - c_i lies beyond a wall.
 //
-// The step kernel is HBM-bound (no dense contraction, so no MFMA): one
-// workgroup owns TX columns and marches up a band of H rows.  For each row it
-// pulls the 18 populations of the next row (kept in registers until that row
-// is collided), writes rho_A, rho_B of that row into a 4-row LDS ring, and
-// after one barrier evaluates the force of the current row from the ring
-// (8 neighbours of both components), collides and stores.  The two halo
-// columns of the ring are pulled by lanes 0 and 1; the halo rows above and
-// below the band cost 2/H extra row reads.  Every population is read once
-// and written once per step apart from those halos.
+// Two step passes, both HBM-bound (no dense contraction, so no MFMA):
+//   k_step   one step per pass: a workgroup owns TX columns and marches
+//            through a band of rows; each row's densities go to a 4-row LDS
+//            ring (with two halo columns) from which, after one barrier, the
+//            previous row's force is evaluated, collided and stored.
+//   k_step2  two steps per pass (temporal blocking): a single wave marches a
+//            band computing step t -> t+1 in registers and, two rows behind,
+//            step t+1 -> t+2 from the neighbouring lanes' results (DPP
+//            shifts); populations cross HBM once per two steps.
+// Both evaluate every site through collide_site, so they agree bit for bit.
 //
 // In the FP64 mode every expression is evaluated in the order of the
 // definitions (sums over i in index order, no contraction), so the step is
 // reproducible bit for bit by a plain CPU implementation of the same
 // equations.
+//
+// Analysis kernels (Sec. 3): the field pass (k_step with FIELDS), energy
+// averages (k_reduce_rows / k_reduce_final), the kinetic-energy budget
+// (k_budget_rows), the interface crossings (k_interface_rows) and the
+// connected components of the two phases (k_cc_*).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -510,7 +520,6 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
        FieldOut fo)
 {
     using Q = Tr<ST>;
-    using T = typename Q::T;
     using C = typename Q::C;
     constexpr int LW = TX + 2;                  // ring row: TX columns plus two halo columns
     __shared__ double ring[4][2][LW];           // rho_A, rho_B of four consecutive rows
@@ -1118,7 +1127,6 @@ __global__ void k_gather(const Member *__restrict__ members, int mi, double *__r
 {
     const Member &M = members[mi];
     using Q = Tr<ST>;
-    using T = typename Q::T;
     const int64_t n = (int64_t)M.nx * M.ny;
     const void *src = M.f[cur];
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
