@@ -13,6 +13,14 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long CPU physics check (still part of the CPU suite)")
 
 
+def paper_value(key):
+    """A number the paper prints (tests/golden/paper_values.json, with its
+    citation there)."""
+    import json
+    with open(os.path.join(ROOT, "tests", "golden", "paper_values.json")) as fh:
+        return json.load(fh)[key]["value"]
+
+
 @pytest.fixture(scope="session")
 def orc():
     import oracle

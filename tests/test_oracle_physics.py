@@ -11,7 +11,12 @@ a wrong streaming direction or a misplaced wall.
 import numpy as np
 import pytest
 
+from conftest import paper_value
+
 CS2 = 1.0 / 3.0
+TAU_P = paper_value("tau")               # the paper's relaxation time
+G_IMM = paper_value("G_immiscible")
+G_MIS = paper_value("G_miscible")
 
 
 def _mode_amplitude(v, k):
@@ -23,7 +28,7 @@ def _decay_rate(ts, amps):
     return -np.polyfit(np.asarray(ts, float), np.log(np.asarray(amps)), 1)[0]
 
 
-@pytest.mark.parametrize("tau", [0.53, 1.0])
+@pytest.mark.parametrize("tau", [TAU_P, 1.0])
 def test_shear_wave_viscosity(orc, tau):
     """Sec. 2: nu = c_s^2 (tau - 1/2), so nu = 0.01 at the paper's tau = 0.53.
     A shear wave u_x = U sin(2 pi y / ny) in a periodic box decays as
@@ -43,6 +48,8 @@ def test_shear_wave_viscosity(orc, tau):
         ts.append(j * dt)
         amps.append(_mode_amplitude(orc.macro(p, f)["ux"][:, 0], k))
     assert _decay_rate(ts, amps) / (k * k) == pytest.approx(nu, rel=0.01)
+    if tau == TAU_P:
+        assert _decay_rate(ts, amps) / (k * k) == pytest.approx(paper_value("nu"), rel=0.01)
 
 
 def test_channel_mode_decay_places_the_walls(orc):
@@ -88,7 +95,7 @@ def _mutual_diffusivity(orc, tau, G, forcing=0, rho=1.1, ny=64, steps=None):
     return _decay_rate(ts, amps) / (k * k)
 
 
-@pytest.mark.parametrize("tau,G", [(0.53, 0.0), (0.53, 0.0805), (1.0, 0.3), (1.0, 0.6)])
+@pytest.mark.parametrize("tau,G", [(TAU_P, 0.0), (TAU_P, G_MIS), (1.0, 0.3), (1.0, 0.6)])
 def test_mutual_diffusivity_matches_paper_formula(orc, tau, G):
     """Sec. 2 estimates the diffusion coefficient of the mixture as
     D = c_s^2 [(tau - 1/2) - rho tau G_AB / 2], about 0.002 for the miscible
@@ -96,10 +103,10 @@ def test_mutual_diffusivity_matches_paper_formula(orc, tau, G):
     50/50 mixture of total density rho decays as exp(-D k^2 t).  The formula's
     tau-dependence is that of the velocity-shift forcing of Eq. 3."""
     D = _mutual_diffusivity(orc, tau, G)
-    expect = CS2 * ((tau - 0.5) - 1.1 * tau * G / 2)
+    expect = CS2 * ((tau - 0.5) - paper_value("rho_pure") * tau * G / 2)
     assert D == pytest.approx(expect, rel=0.02)
-    if (tau, G) == (0.53, 0.0805):
-        assert D == pytest.approx(0.002, rel=0.15)
+    if (tau, G) == (TAU_P, G_MIS):
+        assert D == pytest.approx(paper_value("diffusivity_miscible"), rel=0.15)
 
 
 def test_guo_forcing_diffusivity(orc):
@@ -145,7 +152,7 @@ def _flat_interfaces(orc, tau, G, heavy, trace, ny=32, steps=60000):
 def paper_flat(orc):
     """Paper's immiscible parameters (tau = 0.53, G = 0.1381), each bulk of
     total density 1.1 (one reading of the paper's pure densities 1.10)."""
-    return _flat_interfaces(orc, 0.53, 0.1381, 1.0, 0.1)
+    return _flat_interfaces(orc, TAU_P, G_IMM, 1.0, 0.1)
 
 
 def test_coexistence_about_nine_percent(paper_flat):
@@ -160,6 +167,7 @@ def test_coexistence_about_nine_percent(paper_flat):
     frac_A_phase = b[ny // 2] / a[ny // 2]
     frac_B_phase = a[0] / b[0]
     assert 0.05 < frac_A_phase < 0.12
+    assert frac_A_phase == pytest.approx(paper_value("minority_fraction"), abs=0.03)
     assert frac_B_phase == pytest.approx(frac_A_phase, rel=1e-6)
 
 
@@ -175,6 +183,7 @@ def test_interface_width_about_three_nodes(paper_flat):
     y10 = np.interp(lo + 0.1 * (hi - lo), seg, y)
     y90 = np.interp(lo + 0.9 * (hi - lo), seg, y)
     assert 2.0 < y90 - y10 < 4.5
+    assert y90 - y10 == pytest.approx(paper_value("interface_width"), abs=1.5)
 
 
 def _laplace(orc, tau, G, heavy, trace, N, radii, relax, average):
@@ -227,7 +236,7 @@ def test_laplace_law_at_paper_parameters(orc):
     (-20 %); the check asks for dp R constant (R^2 >= 0.999, small intercept),
     sigma within 25 % of the quoted value, and sigma within 15 % of the flat
     interface stress integral of Eq. 13-14."""
-    tau, G = 0.53, 0.1381
+    tau, G = TAU_P, G_IMM
     a, b = _flat_interfaces(orc, tau, G, 1.1, 0.1)
     heavy, trace = a[16], b[16]
     res = _laplace(orc, tau, G, heavy, trace, 96, (10, 14, 18, 24), 2000, 8000)
@@ -236,7 +245,7 @@ def test_laplace_law_at_paper_parameters(orc):
     r2 = np.corrcoef(1 / R, dp)[0, 1] ** 2
     assert r2 >= 0.999
     assert abs(icpt) <= 0.1 * dp.min()
-    assert slope == pytest.approx(0.0059, rel=0.25)
+    assert slope == pytest.approx(paper_value("sigma"), rel=0.25)
     assert slope == pytest.approx(_sigma_stress(tau, G, a, b), rel=0.15)
 
 
