@@ -27,6 +27,8 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 FORCE_SHIFT = 0
 FORCE_GUO = 1
+PSI_MIRROR = 0
+PSI_ZERO = 1
 
 NQ = 9
 
@@ -47,7 +49,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("forcing", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
                 ("tau", ctypes.c_double * 2), ("G", ctypes.c_double),
-                ("g", ctypes.c_double * 4)]
+                ("g", ctypes.c_double * 4), ("Gw", ctypes.c_double * 2),
+                ("psi_wall", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _lib = None
@@ -89,7 +92,10 @@ def _ptr(a: np.ndarray | None):
 @dataclass
 class Params:
     """Model parameters of one lattice (Sec. 2).  ``g`` holds the body
-    acceleration of each component; Eq. 7 is gA = (0, -g~), gB = (0, +g~)."""
+    acceleration of each component; Eq. 7 is gA = (0, -g~), gB = (0, +g~).
+    ``G_wall`` are the fluid-boundary couplings (G_Ab, G_Bb) of Eq. 6;
+    ``wall_psi`` selects psi on the boundary nodes in Eq. 5 (PSI_MIRROR: the
+    adjacent fluid row; PSI_ZERO: zero)."""
     nx: int
     ny: int
     tau: tuple = (1.0, 1.0)
@@ -97,6 +103,8 @@ class Params:
     g: tuple = ((0.0, 0.0), (0.0, 0.0))
     forcing: int = FORCE_SHIFT
     periodic_y: bool = False
+    G_wall: tuple = (0.0, 0.0)
+    wall_psi: int = 0
 
     def c(self) -> _Params:
         p = _Params()
@@ -108,6 +116,8 @@ class Params:
         flat = [float(self.g[0][0]), float(self.g[0][1]), float(self.g[1][0]), float(self.g[1][1])]
         for k in range(4):
             p.g[k] = flat[k]
+        p.Gw[0], p.Gw[1] = float(self.G_wall[0]), float(self.G_wall[1])
+        p.psi_wall = int(self.wall_psi)
         return p
 
 

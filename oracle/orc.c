@@ -34,9 +34,13 @@
  *     solution of the isotropy conditions of Eq. 4 with c_s^2 = 1/3;
  *   - solid top and bottom use halfway bounce-back (walls half a link
  *     outside rows 0 and ny-1, zero wall velocity);
- *   - the neighbour density in Eq. 5 across a wall is the density of the
- *     adjacent fluid row (mirror), so that a uniform fluid feels no wall
- *     force, consistent with the neutral wetting G_Ab = G_Bb = 0 of Sec. 2;
+ *   - the neighbour density in Eq. 5 across a wall is by default the
+ *     density of the adjacent fluid row (mirror), so that a uniform fluid
+ *     feels no wall force, consistent with the neutral wetting
+ *     G_Ab = G_Bb = 0 of Sec. 2; psi = 0 on the boundary nodes is the
+ *     alternative (psi_wall = 1);
+ *   - the boundary nodes S = 1 of Eq. 6 are the rows y = -1 and y = ny, so
+ *     the fluid-boundary force acts on rows 0 and ny-1 only;
  *   - the sign of Eq. 5 is kept (G > 0 repels A from B);
  *   - besides the paper's velocity-shift forcing (Eq. 2-3) the oracle offers
  *     Guo forcing (Guo, Zheng and Shi 2002) with the common velocity
@@ -72,6 +76,10 @@ typedef struct {
     double G;           /* coupling G_AB of Eq. 5 */
     double g[4];        /* body acceleration per component: gA_x, gA_y, gB_x, gB_y;
                            Eq. 7 is gA = (0, -g~), gB = (0, +g~) */
+    double Gw[2];       /* fluid-boundary couplings G_Ab, G_Bb of Eq. 6 */
+    int32_t psi_wall;   /* psi on boundary nodes in Eq. 5: 0 = the adjacent
+                           fluid row (mirror), 1 = zero */
+    int32_t pad_;
 } orc_params;
 
 static inline size_t fidx(const orc_params *p, int s, int i, int y, int x)
@@ -171,26 +179,35 @@ static void moments(const orc_params *p, const double *f, double *rho, double *j
             }
 }
 
+/* Solid indicator S of Eq. 6: with walls, the boundary nodes are the rows
+ * y = -1 and y = ny just outside the fluid. */
+static inline int solid_row(const orc_params *p, int y)
+{
+    return !p->periodic_y && (y < 0 || y >= p->ny);
+}
+
 /* Pseudopotential psi_s = rho_s (the choice stated under Eq. 5) at a lattice
  * point that may lie one row beyond a wall: x wraps; y either wraps
- * (periodic) or mirrors onto the adjacent fluid row. */
+ * (periodic), or on a boundary node psi is that of the adjacent fluid row
+ * (mirror) or zero, as p->psi_wall selects. */
 static inline double psi_at(const orc_params *p, const double *rho_s, int y, int x)
 {
     x = wrap(x, p->nx);
-    if (p->periodic_y)
+    if (p->periodic_y) {
         y = wrap(y, p->ny);
-    else if (y < 0)
-        y = 0;
-    else if (y >= p->ny)
-        y = p->ny - 1;
+    } else if (solid_row(p, y)) {
+        if (p->psi_wall) return 0.0;
+        y = y < 0 ? 0 : p->ny - 1;
+    }
     return rho_s[sidx(p, y, x)];
 }
 
-/* Eq. 5 + Eq. 7 per unit mass: with psi_s = rho_s the force
- * F_s = -G rho_s sum_i w_i psi_sbar(x + c_i) c_i + rho_s g_s is rho_s a_s
- * with the acceleration a_s = -G sum_i w_i rho_sbar(x + c_i) c_i + g_s (the
- * fluid-boundary term of Eq. 6 vanishes for G_Ab = G_Bb = 0).  This writes
- * a_s; F_s = rho_s a_s where the force itself is needed. */
+/* Eq. 5 + Eq. 7 + Eq. 6 per unit mass: with psi_s = rho_s the force
+ * F_s = -G rho_s sum_i w_i psi_sbar(x + c_i) c_i + rho_s g_s
+ *       - G_sb rho_s sum_i w_i S(x + c_i) c_i
+ * is rho_s a_s with the acceleration
+ * a_s = (-G sum_i w_i psi_sbar(x + c_i) c_i + g_s) - G_sb sum_i w_i S(x + c_i) c_i.
+ * This writes a_s; F_s = rho_s a_s where the force itself is needed. */
 static void accelerations(const orc_params *p, const double *rho, double *ax, double *ay)
 {
     const int nx = p->nx, ny = p->ny;
@@ -206,8 +223,15 @@ static void accelerations(const orc_params *p, const double *rho, double *ax, do
                     sx += W[i] * ps * CX[i];
                     sy += W[i] * ps * CY[i];
                 }
-                ax[s * n + sidx(p, y, x)] = -p->G * sx + p->g[2 * s + 0];
-                ay[s * n + sidx(p, y, x)] = -p->G * sy + p->g[2 * s + 1];
+                /* Eq. 6: boundary nodes among the neighbours */
+                double wx = 0.0, wy = 0.0;
+                for (int i = 0; i < NQ; ++i) {
+                    double S = solid_row(p, y + CY[i]) ? 1.0 : 0.0;
+                    wx += W[i] * S * CX[i];
+                    wy += W[i] * S * CY[i];
+                }
+                ax[s * n + sidx(p, y, x)] = (-p->G * sx + p->g[2 * s + 0]) - p->Gw[s] * wx;
+                ay[s * n + sidx(p, y, x)] = (-p->G * sy + p->g[2 * s + 1]) - p->Gw[s] * wy;
             }
 }
 
