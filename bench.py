@@ -61,11 +61,11 @@ def storage_code(lb, name):
     return {"f64": lb.F64, "f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[name]
 
 
-def lattice_for(lb, workloads, storage, tile=(0, 0), stream=None, graph_chunk=100, spp=0):
+def lattice_for(lb, workloads, storage, tile=(0, 0), stream=None, graph_chunk=100, spp=0, **walls):
     members = []
     for wl in workloads:
         rA, rB = wl.densities()
-        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity))
+        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity, **walls))
     return lb.Lattice(members, forcing=lb.FORCE_SHIFT, storage=storage, tile_x=tile[0], tile_h=tile[1],
                       graph_chunk=graph_chunk, stream=stream, steps_per_pass=spp)
 
@@ -132,17 +132,20 @@ def cpu_baseline(wl, target_s: float = 40.0) -> dict:
                       f"(FP64, OpenMP over rows, {dt:.1f} s)"}
 
 
-def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0):
+def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0, **walls):
     wl = inputs.LARGE_10000x5000
-    lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream, spp=spp)
+    lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream, spp=spp, **walls)
     tile, got = lat.tile_shape(), lat.steps_per_pass
     ms, _ = time_steps(lat, steps, warmup, stream)
     release(lat)
     sites = wl.nx * wl.ny
     mlups = sites / (ms / 1e3) / 1e6
-    return {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "steps_per_pass": got,
-            "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": BYTES_PER_LU[name] // got,
-            "hbm_frac": hbm_frac(name, got, ms, sites)}
+    out = {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "steps_per_pass": got,
+           "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": BYTES_PER_LU[name] // got,
+           "hbm_frac": hbm_frac(name, got, ms, sites)}
+    if walls:
+        out["walls"] = {k: list(v) if isinstance(v, tuple) else v for k, v in walls.items()}
+    return out
 
 
 def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
@@ -272,6 +275,10 @@ def main() -> int:
                 out["storage_variants"].append(variant_line(lb, inputs, name, stream))
         log("ensemble of 16")
         out["ensemble"] = ensemble_line(lb, inputs, stream)
+        # wetting walls (Eq. 6 force, psi = 0 on boundary nodes): the wall-term kernels
+        log("wetting walls")
+        out["wetting_walls"] = variant_line(lb, inputs, args.storage, stream, G_wall=(0.05, -0.05),
+                                            wall_psi=lb.PSI_ZERO)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl)

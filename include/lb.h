@@ -75,11 +75,19 @@ extern "C" {
 #define LB_BF16S 3
 
 /* Top/bottom boundary.  LB_WALLS: halfway bounce-back, no slip, walls half a
- * link outside rows 0 and ny-1, neighbour density across a wall taken from
- * the adjacent row (neutral wetting, G_sb = 0 of Eq. 6).  LB_PERIODIC_Y:
- * periodic in y (validation runs only). */
+ * link outside rows 0 and ny-1; the boundary nodes (S = 1 in Eq. 6) are the
+ * rows y = -1 and y = ny.  LB_PERIODIC_Y: periodic in y (validation runs
+ * only; no boundary nodes). */
 #define LB_WALLS 0
 #define LB_PERIODIC_Y 1
+
+/* psi of the other component on boundary nodes in the Shan-Chen sum of
+ * Eq. 5.  LB_PSI_MIRROR: the density of the adjacent fluid row, so that a
+ * uniform fluid feels no wall force (the neutral wetting of Sec. 2 with
+ * G_Ab = G_Bb = 0).  LB_PSI_ZERO: zero (the solid holds no fluid); wetting is
+ * then set by G_Ab, G_Bb of Eq. 6. */
+#define LB_PSI_MIRROR 0
+#define LB_PSI_ZERO 1
 
 #define LB_MAX_MEMBERS 64
 
@@ -95,6 +103,12 @@ typedef struct lb_member {
     double rho0[2];          /* LB_F16S / LB_BF16S only: reference densities of the
                                 shift w_i rho0_s; 0 selects the mean initial density,
                                 a negative value stores f_i unshifted */
+    double G_wall[2];        /* fluid-boundary couplings G_Ab, G_Bb of Eq. 6 (finite;
+                                used with LB_WALLS): row 0 gets the acceleration
+                                +G_sb/6 and row ny-1 -G_sb/6 along y (exactly
+                                -G_sb sum_i w_i S(x + c_i) c_i); G > 0 repels */
+    int32_t wall_psi;        /* LB_PSI_MIRROR (0) or LB_PSI_ZERO */
+    int32_t reserved;        /* must be 0 */
 } lb_member;
 
 typedef struct lb_config {

@@ -28,6 +28,10 @@ struct alignas(256) Member {
     double tau[2], itau[2];  // relaxation times and their reciprocals
     double G;                // Shan-Chen coupling
     double g[2][2];          // body acceleration per component
+    double aw[2][2];         // Eq. 6 wall acceleration a_s,y of component s on row 0 ([s][0])
+                             //   and row ny - 1 ([s][1]); its x part is exactly 0
+    int32_t wall_force;      // 1: aw applies (walls and some G_sb != 0)
+    int32_t psi_zero;        // 1: psi = 0 on boundary nodes in Eq. 5; 0: psi of the wall row
     float shift[2][NQ];      // 16-bit modes: w_i rho0_s; else 0
     float scale[2][NQ];      // 16-bit modes: power-of-two scale; else 1
     float iscale[2][NQ];     // 1 / scale
@@ -37,7 +41,12 @@ struct alignas(256) Member {
 // Storage modes (values equal the LB_F64 .. LB_BF16S constants of lb.h).
 enum StorageMode { ST_F64 = 0, ST_F32 = 1, ST_F16S = 2, ST_BF16S = 3 };
 enum Forcing { FORCE_SHIFT = 0, FORCE_GUO = 1 };
-enum BcY { BC_WALLS = 0, BC_PERIODIC = 1 };
+// Boundary variant of the step kernels.  BC_WALLS and BC_PERIODIC equal
+// LB_WALLS and LB_PERIODIC_Y.  BC_WALLS_WET is the walls variant that also
+// reads the Eq. 6 wall force and the psi of boundary nodes from the member
+// table; the plain BC_WALLS kernels (neutral walls: no wall force, psi of the
+// wall row) keep the registers those terms would cost.
+enum BcY { BC_WALLS = 0, BC_PERIODIC = 1, BC_WALLS_WET = 2 };
 
 // Outputs of the field (macroscopic) pass: [ny][nx] doubles, any may be null.
 struct FieldOut {
@@ -47,3 +56,15 @@ struct FieldOut {
 constexpr int RED_NQ = 9;  // per-row partial sums kept by the reduction
 
 }  // namespace lbk
+
+// Host runtime helpers shared by the 2D and 3D entry points.
+namespace lbrt {
+// Records the message returned by lb_last_error and returns code.
+__attribute__((visibility("hidden"), format(printf, 2, 3))) int32_t fail(int32_t code, const char *fmt, ...);
+}  // namespace lbrt
+
+#define HIP_TRY(expr)                                                                                      \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess) return lbrt::fail(LB_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)

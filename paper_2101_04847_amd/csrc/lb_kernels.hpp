@@ -4,10 +4,11 @@
 // Method (paper Sec. 2): per component s, rho_s = sum_i f_i^s (Eq. 1);
 // Shan-Chen force F_s = -G rho_s sum_i w_i rho_sbar(x + c_i) c_i (Eq. 5) plus
 // buoyancy rho_s g_s (Eq. 7), i.e. rho_s a_s with the acceleration
-// a_s = -G sum_i w_i rho_sbar(x + c_i) c_i + g_s; common velocity weighted by
-// 1/tau_s (Eq. 1); BGK relaxation towards f^eq(rho_s, u + tau_s a_s)
-// (Eq. 2-3) or Guo forcing; streaming with periodic x and halfway
-// bounce-back walls.
+// a_s = -G sum_i w_i rho_sbar(x + c_i) c_i + g_s, on the two wall rows plus
+// the fluid-boundary term of Eq. 6; common velocity weighted by 1/tau_s
+// (Eq. 1); BGK relaxation towards f^eq(rho_s, u + tau_s a_s) (Eq. 2-3) or Guo
+// forcing; streaming with periodic x and halfway bounce-back walls.  Beyond a
+// wall psi is that of the wall row (mirror) or zero.
 //
 // Storage: per member two buffers of row blocks [y][s][i][pitch] (the 18
 // row segments of one lattice row adjacent, x fastest, pitch a multiple of
@@ -41,21 +42,7 @@
 #include <stdint.h>
 
 #include "lb_internal.hpp"
-
-// Tuning switches (compile-time).
-#ifndef LBK_ALT_DIR
-#define LBK_ALT_DIR 1
-#endif
-#ifndef LBK_HALO_SPLIT
-#define LBK_HALO_SPLIT 1
-#endif
-#ifndef LBK_PIPE
-#define LBK_PIPE 1
-#endif
-#ifndef LBK_NT_STORE
-#define LBK_NT_STORE 1
-#endif
-
+#include "lb_memory.hpp"
 
 namespace lbk {
 
@@ -70,126 +57,6 @@ __host__ __device__ constexpr double wgt(int i) { return i == 0 ? 4.0 / 9.0 : (i
 
 static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis opposites");
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
-
-// ---------------------------------------------------------------------------
-// Pointers into device global memory (address space 1).  The population
-// buffers are reached through the member table, so without this the compiler
-// cannot tell them from LDS and falls back to flat accesses.
-#define LBK_GLOBAL __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ LBK_GLOBAL T *gp(void *p) { return (LBK_GLOBAL T *)p; }
-
-// Element at a uniform base plus a per-lane 32-bit byte offset: the form the
-// hardware addresses with a scalar base register and one vector register.
-template <class T>
-__device__ __forceinline__ T ldg(const LBK_GLOBAL T *base, unsigned byte_off)
-{
-    return *(const LBK_GLOBAL T *)((const LBK_GLOBAL char *)base + byte_off);
-}
-template <class T>
-__device__ __forceinline__ LBK_GLOBAL T *at(LBK_GLOBAL T *base, unsigned byte_off)
-{
-    return (LBK_GLOBAL T *)((LBK_GLOBAL char *)base + byte_off);
-}
-
-// Buffer resources.  Populations are stored in row blocks: the 18 segments
-// f_i^s(., y) of lattice row y are adjacent, so one 128-bit resource spans a
-// whole row block; a load adds a uniform byte offset (which population) and a
-// per-lane byte offset (which column).  Accesses outside the resource read 0
-// and write nothing.
-constexpr int BUF_RAW_DWORD3 = 0x00020000;   // raw (untyped) buffer, gfx9 descriptor word 3
-constexpr int CPOL_NT = 2;                   // non-temporal cache policy bit
-
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-
-__device__ __forceinline__ rsrc_t row_rsrc(const void *buf, int row, int64_t row_bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc((void *)((const char *)buf + (int64_t)row * row_bytes), 0,
-                                             (int)row_bytes, BUF_RAW_DWORD3);
-}
-
-template <class T> __device__ __forceinline__ T bload(rsrc_t r, unsigned voff, unsigned soff);
-template <> __device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-}
-template <> __device__ __forceinline__ uint16_t bload<uint16_t>(rsrc_t r, unsigned voff, unsigned soff)
-{
-    return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
-}
-
-template <int AUX>
-__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                          voff, soff, AUX);
-}
-template <int AUX>
-__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, AUX);
-}
-template <int AUX>
-__device__ __forceinline__ void bstore(_Float16 v, rsrc_t r, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, AUX);
-}
-template <int AUX>
-__device__ __forceinline__ void bstore(uint16_t v, rsrc_t r, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, AUX);
-}
-
-// ---------------------------------------------------------------------------
-// Storage traits: element type T in memory, arithmetic type C of the collision.
-template <int ST> struct Tr;
-
-template <> struct Tr<ST_F64> {
-    using T = double;
-    using C = double;
-    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
-    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
-};
-
-template <> struct Tr<ST_F32> {
-    using T = float;
-    using C = float;
-    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
-    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
-};
-
-// IEEE binary16 holding q = (f - shift) * scale; f = shift + q / scale.  The
-// scales are powers of two, so q * (1/scale) and f * scale are exact and the
-// fused forms below round exactly like the two-operation definitions
-// (nss = -shift * scale).
-template <> struct Tr<ST_F16S> {
-    using T = _Float16;
-    using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf((float)v, iscale, shift); }
-    static __device__ __forceinline__ T enc(C v, float nss, float scale) { return (_Float16)fmaf(v, scale, nss); }
-};
-
-// bfloat16 (kept as raw 16-bit patterns) holding the same shifted, scaled q;
-// the conversion rounds to nearest even (gfx950 converts in hardware).
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-template <> struct Tr<ST_BF16S> {
-    using T = uint16_t;
-    using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf(bf16_to_f32(v), iscale, shift); }
-    static __device__ __forceinline__ T enc(C v, float nss, float scale)
-    {
-        return __builtin_bit_cast(uint16_t, (__bf16)fmaf(v, scale, nss));
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Pull the 18 pre-collision populations f(t) of column c, row y from the
@@ -302,15 +169,26 @@ __device__ __forceinline__ void sc_sum(double p1, double p2, double p3, double p
     Sy = sy;
 }
 
+// Which Eq. 6 wall acceleration row y takes: 0 (row 0), 1 (row ny - 1), or
+// -1 (none: an interior row, periodic y, or G_Ab = G_Bb = 0).  The boundary
+// nodes are the rows just outside the lattice, so only the wall rows see them.
+template <int BCY>
+__device__ __forceinline__ int wall_row(const Member &M, int y)
+{
+    if (BCY != BC_WALLS_WET || !M.wall_force) return -1;
+    return y == 0 ? 0 : (y == M.ny - 1 ? 1 : -1);
+}
+
 // Collision of one site (Eq. 1-3 and the BGK relaxation of Eq. 2, or Guo
 // forcing) given the pulled populations cur_f, the densities rho_c and the
 // Shan-Chen sums S of the other component (S[s] belongs to component s, so
-// component s feels S[1 - s]).  Each post-collision value is handed to
-// emit(s, i, post) in the arithmetic type of the storage mode.
+// component s feels S[1 - s]); wrow selects the wall acceleration of Eq. 6
+// (wall_row).  Each post-collision value is handed to emit(s, i, post) in
+// the arithmetic type of the storage mode.
 template <int ST, int FORCING, class Emit>
 __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<ST>::C (&cur_f)[2][NQ],
                                              const double (&rho_c)[2], const double (&Sx)[2], const double (&Sy)[2],
-                                             Emit &&emit)
+                                             int wrow, Emit &&emit)
 {
     using C = typename Tr<ST>::C;
     double jx[2], jy[2];
@@ -318,13 +196,14 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
     for (int s = 0; s < 2; ++s) momentum(cur_f[s], jx[s], jy[s]);
     if constexpr (ST == ST_F64) {
         // FP64: the definitions evaluated in their written order.  With
-        // psi_s = rho_s, Eq. 5 + Eq. 7 give F_s = rho_s a_s with the
-        // acceleration a_s = -G S_sbar + g_s.
+        // psi_s = rho_s, Eq. 5 + Eq. 7 (+ Eq. 6 on a wall row) give
+        // F_s = rho_s a_s with the acceleration a_s = -G S_sbar + g_s (+ a^w_s).
         double ax[2], ay[2], Fx[2], Fy[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             ax[s] = -M.G * Sx[1 - s] + M.g[s][0];
             ay[s] = -M.G * Sy[1 - s] + M.g[s][1];
+            if (wrow >= 0) ay[s] += M.aw[s][wrow];
             Fx[s] = rho_c[s] * ax[s];
             Fy[s] = rho_c[s] * ay[s];
         }
@@ -389,13 +268,15 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
     } else {
         // Reduced-precision modes: the collision in FP32 with fused
         // multiply-adds.  Densities, the Shan-Chen sums and the
-        // accelerations a_s = -G S_sbar + g_s stay FP64.
+        // accelerations a_s = -G S_sbar + g_s (+ a^w_s) stay FP64.
         float rf[2], ax[2], ay[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             rf[s] = (float)rho_c[s];
             ax[s] = (float)(-M.G * Sx[1 - s] + M.g[s][0]);
-            ay[s] = (float)(-M.G * Sy[1 - s] + M.g[s][1]);
+            double ays = -M.G * Sy[1 - s] + M.g[s][1];
+            if (wrow >= 0) ays += M.aw[s][wrow];
+            ay[s] = (float)ays;
         }
         float ux, uy;
         if (FORCING == FORCE_SHIFT) {
@@ -473,7 +354,7 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
 // ring slots of rows y, y + 1 and y - 1; e is this lane's ring column.
 template <int ST, int FORCING, bool FIELDS, int LW>
 __device__ __forceinline__ void row_update(const Member &M, const double (&ring)[4][2][LW], int s0, int sp, int sm,
-                                           int e, int x, int y, const typename Tr<ST>::C (&cur_f)[2][NQ],
+                                           int e, int x, int y, int wrow, const typename Tr<ST>::C (&cur_f)[2][NQ],
                                            const double (&rho_c)[2], void *dst, const FieldOut &fo)
 {
     using Q = Tr<ST>;
@@ -489,9 +370,11 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             momentum(cur_f[s], jx[s], jy[s]);
-            // F_s = rho_s a_s, a_s = -G S_sbar + g_s   (Eq. 5 + Eq. 7, psi_s = rho_s)
+            // F_s = rho_s a_s, a_s = -G S_sbar + g_s (+ a^w_s)   (Eq. 5 + Eq. 7 + Eq. 6, psi_s = rho_s)
             Fx[s] = rho_c[s] * (-M.G * Sx[1 - s] + M.g[s][0]);
-            Fy[s] = rho_c[s] * (-M.G * Sy[1 - s] + M.g[s][1]);
+            double ay = -M.G * Sy[1 - s] + M.g[s][1];
+            if (wrow >= 0) ay += M.aw[s][wrow];
+            Fy[s] = rho_c[s] * ay;
         }
         const double rt = rho_c[0] + rho_c[1];
         // hydrodynamic velocity (sum_s j_s + sum_s F_s / 2) / rho
@@ -507,7 +390,7 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
         const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
         const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
         const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
-        collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, [&](int s, int i, C post) {
+        collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, wrow, [&](int s, int i, C post) {
             bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
                                                 (unsigned)s * wss + (unsigned)i * wis);
         });
@@ -548,6 +431,8 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         const int dir = 1;
 #endif
         const int yfirst = dir > 0 ? y0 : y0 + nrows - 1;
+        // psi beyond a wall: that of the wall row (mirror) or zero
+        const bool pz = BCY == BC_WALLS_WET && M.psi_zero;
 
         const int x = x0 + lane;
         const bool active = x < nx;
@@ -605,11 +490,11 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         }
         {
             int yb = yfirst - dir;
-            const bool mirror = ((yb < 0) || (yb >= ny)) && (BCY == BC_WALLS);
+            const bool mirror = ((yb < 0) || (yb >= ny)) && (BCY != BC_PERIODIC);
             if (yb < 0) yb += ny;
             if (yb >= ny) yb -= ny;
             {
-                double r0 = rho_c[0], r1 = rho_c[1];
+                double r0 = pz ? 0.0 : rho_c[0], r1 = pz ? 0.0 : rho_c[1];
                 if (!mirror) {
                     C hf[2][NQ];
                     pull_site<ST, BCY>(src, M, yb, lcol, hf);
@@ -620,7 +505,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 ring[0][1][lane + 1] = r1;
             }
             if (hcol >= 0) {
-                double r0 = rho_h[0], r1 = rho_h[1];
+                double r0 = pz ? 0.0 : rho_h[0], r1 = pz ? 0.0 : rho_h[1];
                 if (!mirror) {
                     C hf[2][NQ];
                     pull_site<ST, BCY>(src, M, yb, hcol, hf);
@@ -634,7 +519,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
         // request the row ahead of the first one (march index 1)
         {
             int y1 = yfirst + dir;
-            const bool mirror = ((y1 < 0) || (y1 >= ny)) && (BCY == BC_WALLS);
+            const bool mirror = ((y1 < 0) || (y1 >= ny)) && (BCY != BC_PERIODIC);
             if (y1 < 0) y1 += ny;
             if (y1 >= ny) y1 -= ny;
             if (!mirror) pull_site<ST, BCY>(src, M, y1, lcol, fb);
@@ -646,15 +531,15 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             const int y = yfirst + dir * r;
             int yn = y + dir;                   // the row ahead
             const int sn = (r + 2) & 3;         // its ring slot
-            const bool mirror = ((yn < 0) || (yn >= ny)) && (BCY == BC_WALLS);
+            const bool mirror = ((yn < 0) || (yn >= ny)) && (BCY != BC_PERIODIC);
             if (yn < 0) yn += ny;
             if (yn >= ny) yn -= ny;
             // evaluated on every path (mirror rows then discard it) so that
             // nf's loads are known to have landed before nf becomes current
             double rn[2] = {density(nf[0]), density(nf[1])};
             if (mirror) {
-                rn[0] = rho_c[0];
-                rn[1] = rho_c[1];
+                rn[0] = pz ? 0.0 : rho_c[0];
+                rn[1] = pz ? 0.0 : rho_c[1];
             }
             ring[sn][0][lane + 1] = rn[0];
             ring[sn][1][lane + 1] = rn[1];
@@ -665,13 +550,13 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                     rho_h[0] = density(hf[0]);
                     rho_h[1] = density(hf[1]);
                 }
-                ring[sn][0][hent] = rho_h[0];
-                ring[sn][1][hent] = rho_h[1];
+                ring[sn][0][hent] = (mirror && pz) ? 0.0 : rho_h[0];
+                ring[sn][1][hent] = (mirror && pz) ? 0.0 : rho_h[1];
             }
             if (r + 2 <= nrows) {
                 // the row after next: inside the band, or the halo row beyond it
                 int y2 = y + 2 * dir;
-                const bool mirror2 = ((y2 < 0) || (y2 >= ny)) && (BCY == BC_WALLS);
+                const bool mirror2 = ((y2 < 0) || (y2 >= ny)) && (BCY != BC_PERIODIC);
                 if (y2 < 0) y2 += ny;
                 if (y2 >= ny) y2 -= ny;
                 if (!mirror2) pull_site<ST, BCY>(src, M, y2, lcol, pf);
@@ -681,7 +566,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 const int s0 = (r + 1) & 3;
                 const int sp = dir > 0 ? sn : (r & 3);
                 const int sm = dir > 0 ? (r & 3) : sn;
-                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, cf, rho_c, dst, fo);
+                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, wall_row<BCY>(M, y), cf, rho_c, dst, fo);
             }
             rho_c[0] = rn[0];
             rho_c[1] = rn[1];
@@ -725,11 +610,11 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             // mirror of the first row
             int yb = yfirst - dir;
             const bool outside = (yb < 0) || (yb >= ny);
-            const bool mirror = outside && (BCY == BC_WALLS);
+            const bool mirror = outside && (BCY != BC_PERIODIC);
             if (yb < 0) yb += ny;
             if (yb >= ny) yb -= ny;
             if (col >= 0) {
-                double r0 = rho_c[0], r1 = rho_c[1];
+                double r0 = pz ? 0.0 : rho_c[0], r1 = pz ? 0.0 : rho_c[1];
                 if (!mirror) {
                     C hf[2][NQ];
                     pull_site<ST, BCY>(src, M, yb, col, hf);
@@ -740,7 +625,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 ring[0][1][lane + 1] = r1;
             }
             if (hcol >= 0) {
-                double r0 = rho_h[0], r1 = rho_h[1];
+                double r0 = pz ? 0.0 : rho_h[0], r1 = pz ? 0.0 : rho_h[1];
                 if (!mirror) {
                     C hf[2][NQ];
                     pull_site<ST, BCY>(src, M, yb, hcol, hf);
@@ -758,10 +643,10 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
             int yn = y + dir;                   // the row ahead
             const int sn = (r + 2) & 3;         // its ring slot
             const bool outside = (yn < 0) || (yn >= ny);
-            const bool mirror = outside && (BCY == BC_WALLS);
+            const bool mirror = outside && (BCY != BC_PERIODIC);
             if (yn < 0) yn += ny;
             if (yn >= ny) yn -= ny;
-            double rn[2] = {rho_c[0], rho_c[1]};
+            double rn[2] = {pz ? 0.0 : rho_c[0], pz ? 0.0 : rho_c[1]};
             if (col >= 0 && !mirror) {
                 pull_site<ST, BCY>(src, M, yn, col, nxt_f);
                 rn[0] = density(nxt_f[0]);
@@ -778,8 +663,8 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                     rho_h[0] = density(hf[0]);
                     rho_h[1] = density(hf[1]);
                 }
-                ring[sn][0][hent] = rho_h[0];
-                ring[sn][1][hent] = rho_h[1];
+                ring[sn][0][hent] = (mirror && pz) ? 0.0 : rho_h[0];
+                ring[sn][1][hent] = (mirror && pz) ? 0.0 : rho_h[1];
             }
             __syncthreads();
 
@@ -788,7 +673,7 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
                 const int s0 = (r + 1) & 3;
                 const int sp = dir > 0 ? sn : (r & 3);
                 const int sm = dir > 0 ? (r & 3) : sn;
-                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, cur_f, rho_c, dst, fo);
+                row_update<ST, FORCING, FIELDS, LW>(M, ring, s0, sp, sm, lane + 1, x, y, wall_row<BCY>(M, y), cur_f, rho_c, dst, fo);
             }
             // rotate: the row ahead becomes current
 #pragma unroll
@@ -890,6 +775,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
     const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
     const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
     auto inside = [&](int v) { return BCY == BC_PERIODIC || (v >= 0 && v < ny); };
+    // psi beyond a wall: that of the wall row (mirror) or zero
+    const bool pz = BCY == BC_WALLS_WET && M.psi_zero;
     auto wrap = [&](int v) {
         if (BCY == BC_PERIODIC) {
             v %= ny;
@@ -941,20 +828,20 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
 #pragma unroll
             for (int i = 0; i < NQ; ++i) out1[s][i] = (C)0;
         if (in_a) {
-            // beyond a wall psi mirrors the wall row
+            // beyond a wall psi is the wall row's (mirror) or zero
             double rb[2], rf[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                rb[s] = in_am ? r1m[s] : r1c[s];
-                rf[s] = in_ap ? r1n[s] : r1c[s];
+                rb[s] = in_am ? r1m[s] : (pz ? 0.0 : r1c[s]);
+                rf[s] = in_ap ? r1n[s] : (pz ? 0.0 : r1c[s]);
             }
             double Sx[2], Sy[2];
             if constexpr (DIR > 0) sc_sums_lanes(rb, r1c, rf, Sx, Sy);
             else sc_sums_lanes(rf, r1c, rb, Sx, Sy);
-            collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, [&](int s, int i, C post) {
+            collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, wall_row<BCY>(M, a), [&](int s, int i, C post) {
                 out1[s][i] = Q::dec(Q::enc(post, M.nss[s][i], M.scale[s][i]), M.shift[s][i], M.iscale[s][i]);
             });
-        } else if (BCY == BC_WALLS) {
+        } else if (BCY != BC_PERIODIC) {
             // row a lies beyond a wall: the pull of row a - DIR takes its
             // c_y = -DIR populations from its own reversed ones (bounce-back)
 #pragma unroll
@@ -967,8 +854,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
         // --- step 2: row p = a - DIR is pulled from the step-1 rows
         const int p = a - DIR;
         const bool pull_p = k >= 2 && inside(p);
-        const bool bb_f = (BCY == BC_WALLS) && !inside(p - DIR);   // Qv holds bounce-back values
-        const bool bb_b = (BCY == BC_WALLS) && !in_a;              // out1 holds bounce-back values
+        const bool bb_f = (BCY != BC_PERIODIC) && !inside(p - DIR);   // Qv holds bounce-back values
+        const bool bb_b = (BCY != BC_PERIODIC) && !in_a;              // out1 holds bounce-back values
         auto pull_row = [&](int s, C (&v)[NQ]) {
             v[0] = P[s][0];
             v[1] = shift_x<1>(P[s][1]);
@@ -997,14 +884,14 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
             double rb[2], rf[2];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                rb[s] = inside(q - DIR) ? r2m[s] : r2c[s];
-                rf[s] = inside(p) ? r2n[s] : r2c[s];
+                rb[s] = inside(q - DIR) ? r2m[s] : (pz ? 0.0 : r2c[s]);
+                rf[s] = inside(p) ? r2n[s] : (pz ? 0.0 : r2c[s]);
             }
             double Sx[2], Sy[2];
             if constexpr (DIR > 0) sc_sums_lanes(rb, r2c, rf, Sx, Sy);
             else sc_sums_lanes(rf, r2c, rb, Sx, Sy);
             const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
-            collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, [&](int s, int i, C post) {
+            collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q), [&](int s, int i, C post) {
                 if (store_ok)
                     bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
                                                         (unsigned)s * wss + (unsigned)i * wis);
@@ -1015,7 +902,7 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
             for (int s = 0; s < 2; ++s) pull_row(s, g[s]);
         }
         // --- rotate the step-1 results (row a becomes the previous row)
-        const bool bb_next = (BCY == BC_WALLS) && in_a && !in_am;   // row a is the first row at a wall
+        const bool bb_next = (BCY != BC_PERIODIC) && in_a && !in_am;   // row a is the first row at a wall
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
 #pragma unroll

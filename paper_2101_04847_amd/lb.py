@@ -26,6 +26,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, 
 FORCE_SHIFT, FORCE_GUO = 0, 1
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 WALLS, PERIODIC_Y = 0, 1
+PSI_MIRROR, PSI_ZERO = 0, 1
 MAX_MEMBERS = 64
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16S: "f16s", BF16S: "bf16s"}
 ELEM_BYTES = {F64: 8, F32: 4, F16S: 2, BF16S: 2}
@@ -38,7 +39,9 @@ class LbMember(ctypes.Structure):
                 ("tau", ctypes.c_double * 2), ("G_AB", ctypes.c_double),
                 ("g", (ctypes.c_double * 2) * 2),
                 ("rhoA0", _dp), ("rhoB0", _dp),
-                ("rho0", ctypes.c_double * 2)]
+                ("rho0", ctypes.c_double * 2),
+                ("G_wall", ctypes.c_double * 2), ("wall_psi", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class LbConfig(ctypes.Structure):
@@ -130,7 +133,9 @@ def last_error() -> str:
 @dataclass
 class Member:
     """One realisation: lattice size, relaxation times, coupling, per-component
-    body accelerations and initial densities ([ny][nx] float64)."""
+    body accelerations and initial densities ([ny][nx] float64).  ``G_wall``
+    are the fluid-boundary couplings (G_Ab, G_Bb) of Eq. 6 and ``wall_psi``
+    the psi of boundary nodes in Eq. 5 (PSI_MIRROR or PSI_ZERO)."""
     nx: int
     ny: int
     rhoA0: np.ndarray
@@ -139,6 +144,8 @@ class Member:
     G: float = 0.0
     g: tuple = ((0.0, 0.0), (0.0, 0.0))
     rho0: tuple = (0.0, 0.0)
+    G_wall: tuple = (0.0, 0.0)
+    wall_psi: int = 0
 
 
 def _member_struct(m: Member, keep: list) -> LbMember:
@@ -158,6 +165,9 @@ def _member_struct(m: Member, keep: list) -> LbMember:
     s.rhoA0 = a.ctypes.data_as(_dp)
     s.rhoB0 = b.ctypes.data_as(_dp)
     s.rho0[0], s.rho0[1] = float(m.rho0[0]), float(m.rho0[1])
+    s.G_wall[0], s.G_wall[1] = float(m.G_wall[0]), float(m.G_wall[1])
+    s.wall_psi = int(m.wall_psi)
+    s.reserved = 0
     return s
 
 
