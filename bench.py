@@ -148,6 +148,36 @@ def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0, **walls)
     return out
 
 
+# algorithmic HBM bytes per 3D site update: the density pass reads 38
+# populations and writes 2 densities (FP64); the collide pass reads 38
+# populations and the densities (each once, the neighbours' from cache) and
+# writes 38 populations
+BYTES_PER_LU_3D = {"f64": 38 * 8 + 16 + 38 * 8 + 16 + 38 * 8, "f32": 38 * 4 + 16 + 38 * 4 + 16 + 38 * 4}
+
+
+def d3q19_line(lb, inputs, stream, storage="f64", steps=100, warmup=10):
+    from paper_2101_04847_amd import lb3
+    w = inputs.D3_384
+    rA, rB = inputs.rt3d_densities(w["nx"], w["ny"], w["nz"], w["seed"])
+    lat = lb3.Lattice3(w["nx"], w["ny"], w["nz"], rA, rB, tau=(w["tau"], w["tau"]), G=w["G"],
+                       g=((0.0, -w["g"], 0.0), (0.0, w["g"], 0.0)), storage=storage_code(lb, storage),
+                       stream=stream)
+    del rA, rB
+    ms, _ = time_steps(lat, steps, warmup, stream, chunk=steps)
+    d = lat.diagnostics()
+    lat.close()
+    del lat
+    import torch
+    torch.cuda.empty_cache()
+    sites = w["nx"] * w["ny"] * w["nz"]
+    mlups = sites / (ms / 1e3) / 1e6
+    bpl = BYTES_PER_LU_3D[storage]
+    return {"workload": w["name"], "storage": storage, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4),
+            "kernels": ["lbk3::k3_density", "lbk3::k3_collide"], "bytes_per_lu": bpl,
+            "hbm_frac": round(bpl * sites / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": d["finite"],
+            "umax": d["umax"]}
+
+
 def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
     wls = inputs.ensemble_16()
     lat = lattice_for(lb, wls, storage_code(lb, storage), stream=stream)
@@ -279,6 +309,11 @@ def main() -> int:
         log("wetting walls")
         out["wetting_walls"] = variant_line(lb, inputs, args.storage, stream, G_wall=(0.05, -0.05),
                                             wall_psi=lb.PSI_ZERO)
+        # the D3Q19 extension on 384^3
+        out["d3q19"] = []
+        for st in ("f64", "f32"):
+            log("d3q19", st)
+            out["d3q19"].append(d3q19_line(lb, inputs, stream, st))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl)

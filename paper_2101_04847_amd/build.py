@@ -13,9 +13,11 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblb.so")
 PROBE = os.path.join(PKG, "bw_probe")
-SOURCES = [os.path.join(CSRC, "lb.hip")]
+SOURCES = [os.path.join(CSRC, "lb.hip"), os.path.join(CSRC, "lb3.hip")]
 HEADERS = [os.path.join(CSRC, "lb_kernels.hpp"), os.path.join(CSRC, "lb_internal.hpp"),
-           os.path.join(ROOT, "include", "lb.h")]
+           os.path.join(CSRC, "lb_memory.hpp"),
+           os.path.join(CSRC, "lb3_kernels.hpp"), os.path.join(ROOT, "include", "lb.h"),
+           os.path.join(ROOT, "include", "lb3.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

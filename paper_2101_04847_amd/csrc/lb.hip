@@ -24,7 +24,7 @@
 
 using namespace lbk;
 
-namespace {
+namespace lbrt {
 
 thread_local std::string g_err;
 
@@ -39,11 +39,11 @@ int32_t fail(int32_t code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(LB_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace lbrt
+
+using lbrt::fail;
+
+namespace {
 
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -84,14 +84,22 @@ StepFn step_for_tx(int k)
     }
 }
 
+template <int ST, int F, bool FIELDS>
+StepFn step_for_bc(int bc, int k)
+{
+    switch (bc) {
+        case BC_WALLS: return step_for_tx<ST, F, BC_WALLS, FIELDS>(k);
+        case BC_PERIODIC: return step_for_tx<ST, F, BC_PERIODIC, FIELDS>(k);
+        default: return step_for_tx<ST, F, BC_WALLS_WET, FIELDS>(k);
+    }
+}
+
+// bc is a kernel boundary variant (BcY, lb_handle::kbc)
 template <int ST, bool FIELDS>
 StepFn step_for(int forcing, int bc, int k)
 {
-    if (forcing == LB_FORCE_SHIFT)
-        return bc == LB_WALLS ? step_for_tx<ST, FORCE_SHIFT, BC_WALLS, FIELDS>(k)
-                              : step_for_tx<ST, FORCE_SHIFT, BC_PERIODIC, FIELDS>(k);
-    return bc == LB_WALLS ? step_for_tx<ST, FORCE_GUO, BC_WALLS, FIELDS>(k)
-                          : step_for_tx<ST, FORCE_GUO, BC_PERIODIC, FIELDS>(k);
+    if (forcing == LB_FORCE_SHIFT) return step_for_bc<ST, FORCE_SHIFT, FIELDS>(bc, k);
+    return step_for_bc<ST, FORCE_GUO, FIELDS>(bc, k);
 }
 
 StepFn pick_step(int storage, int forcing, int bc, int k, bool fields)
@@ -99,10 +107,10 @@ StepFn pick_step(int storage, int forcing, int bc, int k, bool fields)
     if (fields) {
         // the field pass does not depend on the forcing scheme
         switch (storage) {
-            case LB_F64: return step_for<ST_F64, true>(LB_FORCE_SHIFT, bc, k);
-            case LB_F32: return step_for<ST_F32, true>(LB_FORCE_SHIFT, bc, k);
-            case LB_F16S: return step_for<ST_F16S, true>(LB_FORCE_SHIFT, bc, k);
-            default: return step_for<ST_BF16S, true>(LB_FORCE_SHIFT, bc, k);
+            case LB_F64: return step_for_bc<ST_F64, FORCE_SHIFT, true>(bc, k);
+            case LB_F32: return step_for_bc<ST_F32, FORCE_SHIFT, true>(bc, k);
+            case LB_F16S: return step_for_bc<ST_F16S, FORCE_SHIFT, true>(bc, k);
+            default: return step_for_bc<ST_BF16S, FORCE_SHIFT, true>(bc, k);
         }
     }
     switch (storage) {
@@ -115,12 +123,20 @@ StepFn pick_step(int storage, int forcing, int bc, int k, bool fields)
 
 using Step2Fn = void (*)(const Member *, int, int64_t, int64_t, int);
 
+template <int ST, int F>
+Step2Fn step2_for_bc(int bc)
+{
+    switch (bc) {
+        case BC_WALLS: return (Step2Fn)k_step2<ST, F, BC_WALLS>;
+        case BC_PERIODIC: return (Step2Fn)k_step2<ST, F, BC_PERIODIC>;
+        default: return (Step2Fn)k_step2<ST, F, BC_WALLS_WET>;
+    }
+}
+
 template <int ST>
 Step2Fn step2_for(int forcing, int bc)
 {
-    if (forcing == LB_FORCE_SHIFT)
-        return bc == LB_WALLS ? (Step2Fn)k_step2<ST, FORCE_SHIFT, BC_WALLS> : (Step2Fn)k_step2<ST, FORCE_SHIFT, BC_PERIODIC>;
-    return bc == LB_WALLS ? (Step2Fn)k_step2<ST, FORCE_GUO, BC_WALLS> : (Step2Fn)k_step2<ST, FORCE_GUO, BC_PERIODIC>;
+    return forcing == LB_FORCE_SHIFT ? step2_for_bc<ST, FORCE_SHIFT>(bc) : step2_for_bc<ST, FORCE_GUO>(bc);
 }
 
 Step2Fn pick_step2(int storage, int forcing, int bc)
@@ -133,6 +149,7 @@ Step2Fn pick_step2(int storage, int forcing, int bc)
     }
 }
 
+// state conversion depends only on periodic y or walls (an lb_config bc_y)
 template <int ST>
 ScatterFn scatter_for(int bc) { return bc == LB_WALLS ? k_scatter<ST, BC_WALLS> : k_scatter<ST, BC_PERIODIC>; }
 template <int ST>
@@ -197,6 +214,19 @@ bool build_layout(const lb_config *c, Layout &L)
     return true;
 }
 
+// Eq. 6 on a wall row: sum_i w_i S(x + c_i) c_i,y in index order, where the
+// boundary nodes are the row below row 0 (side 0) or above row ny - 1
+// (side 1).  The x part cancels exactly (the two diagonal links).
+double wall_link_sum(int side)
+{
+    double sw = 0.0;
+    for (int i = 0; i < NQ; ++i) {
+        const double S = (side == 0 ? cy(i) < 0 : cy(i) > 0) ? 1.0 : 0.0;
+        sw += wgt(i) * S * cy(i);
+    }
+    return sw;
+}
+
 int32_t validate(const lb_config *c)
 {
     if (!c) return fail(LB_EINVAL, "config is NULL");
@@ -231,6 +261,11 @@ int32_t validate(const lb_config *c)
         for (int s = 0; s < 2; ++s)
             for (int a = 0; a < 2; ++a)
                 if (!std::isfinite(mm.g[s][a])) return fail(LB_EINVAL, "member %d: g[%d][%d] is not finite", m, s, a);
+        for (int s = 0; s < 2; ++s)
+            if (!std::isfinite(mm.G_wall[s])) return fail(LB_EINVAL, "member %d: G_wall[%d] is not finite", m, s);
+        if (mm.wall_psi != LB_PSI_MIRROR && mm.wall_psi != LB_PSI_ZERO)
+            return fail(LB_EINVAL, "member %d: wall_psi = %d is not LB_PSI_MIRROR or LB_PSI_ZERO", m, mm.wall_psi);
+        if (mm.reserved != 0) return fail(LB_EINVAL, "member %d: reserved = %d must be 0", m, mm.reserved);
         if (!mm.rhoA0 || !mm.rhoB0) return fail(LB_EINVAL, "member %d: initial densities are NULL", m);
         if (mm.ny <= 2 * c->diag_trim) return fail(LB_EINVAL, "member %d: ny = %d leaves no rows after trimming %d", m, mm.ny, c->diag_trim);
     }
@@ -251,6 +286,8 @@ struct lb_handle {
     int cur = 0;
     int tile_x = 0;
     int64_t n_items = 0;
+    int kbc = BC_WALLS;             // boundary variant of the step kernels: BC_PERIODIC, BC_WALLS, or
+                                    // BC_WALLS_WET when a member has a wall force or psi = 0 beyond walls
     int steps_per_pass = 1;         // 2: lb_step runs the two-step pass
     int64_t n_items2 = 0;
     int chunk = 0;
@@ -319,14 +356,14 @@ int32_t upload_members(lb_handle *h)
 int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
 {
     if (h->steps_per_pass == 2) {
-        Step2Fn fn2 = pick_step2(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y);
+        Step2Fn fn2 = pick_step2(h->cfg.storage, h->cfg.forcing, h->kbc);
         for (; n >= 2; n -= 2) {
             hipLaunchKernelGGL(fn2, dim3((unsigned)h->n_items2), dim3(64), 0, s, (const Member *)dev_members(h),
                                (int)h->dm.size(), (int64_t)0, h->n_items2, cur);
             cur ^= 1;
         }
     }
-    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(h->tile_x), false);
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->kbc, tx_index(h->tile_x), false);
     const FieldOut none{nullptr, nullptr, nullptr, nullptr};
     for (int64_t k = 0; k < n; ++k) {
         hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items), dim3(h->tile_x), 0, s, (const Member *)dev_members(h),
@@ -380,7 +417,7 @@ int32_t time_shape(lb_handle *h, int tx, const std::vector<int> &th, int reps, f
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
-    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(tx), false);
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->kbc, tx_index(tx), false);
     const FieldOut none{nullptr, nullptr, nullptr, nullptr};
     auto once = [&]() {
         hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items), dim3(tx), 0, h->stream, (const Member *)dev_members(h),
@@ -409,7 +446,7 @@ int32_t time_shape2(lb_handle *h, const std::vector<int> &th, int reps, float &m
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
     HIP_TRY(hipEventCreate(&b));
-    Step2Fn fn = pick_step2(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y);
+    Step2Fn fn = pick_step2(h->cfg.storage, h->cfg.forcing, h->kbc);
     auto once = [&]() {
         hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items2), dim3(64), 0, h->stream, (const Member *)dev_members(h),
                            (int)h->dm.size(), (int64_t)0, h->n_items2, h->cur);
@@ -568,7 +605,7 @@ void set_scales(const lb_config *c, const lb_member &mm, Member &M)
 // ===========================================================================
 extern "C" {
 
-const char *lb_last_error(void) { return g_err.c_str(); }
+const char *lb_last_error(void) { return lbrt::g_err.c_str(); }
 
 size_t lb_workspace_bytes(const lb_config *cfg)
 {
@@ -631,8 +668,17 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
             M.g[s][1] = mm.g[s][1];
         }
         M.G = mm.G_AB;
+        // Eq. 6: a^w_s = -G_sb sum_i w_i S(x + c_i) c_i on the wall rows
+        M.wall_force = cfg->bc_y == LB_WALLS && (mm.G_wall[0] != 0.0 || mm.G_wall[1] != 0.0);
+        M.psi_zero = mm.wall_psi == LB_PSI_ZERO;
+        for (int side = 0; side < 2; ++side) {
+            const double sw = wall_link_sum(side);
+            for (int s = 0; s < 2; ++s) M.aw[s][side] = -(mm.G_wall[s] * sw);
+        }
         set_scales(cfg, mm, M);
+        if (M.wall_force || M.psi_zero) h->kbc = BC_WALLS_WET;
     }
+    if (cfg->bc_y == LB_PERIODIC_Y) h->kbc = BC_PERIODIC;
     plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, std::vector<int>(cfg->n_members, cfg->tile_h ? cfg->tile_h : 16));
     plan_tiles2(h, std::vector<int>(cfg->n_members, 12));
     if ((rc = upload_members(h))) return bail(rc);
@@ -693,7 +739,7 @@ int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, doubl
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
     const Member &M = h->dm[m];
-    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->cfg.bc_y, tx_index(h->tile_x), true);
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->kbc, tx_index(h->tile_x), true);
     FieldOut fo{d_rhoA, d_rhoB, d_ux, d_uy};
     const int64_t n_items = M.item_end - M.item_begin;
     hipLaunchKernelGGL(fn, dim3((unsigned)n_items), dim3(h->tile_x), 0, h->stream, (const Member *)dev_members(h),

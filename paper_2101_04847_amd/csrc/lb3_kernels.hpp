@@ -1,0 +1,403 @@
+// gfx950 kernels of the three-dimensional (D3Q19) two-component Shan-Chen
+// step: the method of Sec. 2 (Eq. 1-7) with the D2Q9 set replaced by D3Q19.
+//
+// Storage: two buffers of row blocks [z][y][s][i][pitch] (the 38 row
+// segments of one lattice row adjacent, x fastest) holding post-collision
+// populations; f(t) is pulled: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) where
+// x - c_i lies beyond a y wall.  A step is two HBM-bound passes with one
+// thread per site and one 64-lane wave per row segment:
+//   k3_density   pulls f(t) and writes rho_A, rho_B ([z][y][2][pitch], FP64);
+//   k3_collide   pulls f(t) again, reads the 18 neighbour densities of the
+//                other component (cache-resident: 16 B per site), forms the
+//                Shan-Chen + body acceleration, the 1/tau-weighted velocity,
+//                the shifted equilibrium and the BGK relaxation, and stores
+//                f*(t) at the site; with FIELDS it writes rho_A, rho_B and the
+//                hydrodynamic velocity instead.
+// All arithmetic is FP64 in both storage modes, every expression in the
+// order of its definition (sums over i in index order, no contraction), so
+// the FP64 mode is reproducible bit for bit by a plain implementation.
+#pragma once
+
+#include "lb_memory.hpp"
+
+namespace lbk3 {
+
+using lbk::bload;
+using lbk::bstore;
+using lbk::row_rsrc;
+using lbk::rsrc_t;
+using lbk::Tr;
+
+constexpr int NQ3 = 19;
+
+// D3Q19: 0 rest; 1..6 axis links +x -x +y -y +z -z; 7..18 edge links in
+// reversed pairs (+x+y, -x-y), (+x-y, -x+y), (+x+z, -x-z), (+x-z, -x+z),
+// (+y+z, -y-z), (+y-z, -y+z).  Weights from the isotropy conditions of Eq. 4.
+__host__ __device__ constexpr int c3x(int i)
+{
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1 : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int c3y(int i)
+{
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1 : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int c3z(int i)
+{
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1 : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp3(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+static_assert(c3x(opp3(13)) == -1 && c3z(opp3(13)) == 1, "edge opposites");
+static_assert(c3y(opp3(17)) == -1 && c3z(opp3(17)) == 1, "edge opposites");
+
+// One lattice as the kernels see it (passed by value).
+struct Lat3 {
+    int32_t nx, ny, nz, pitch;   // pitch: elements per row segment (nx rounded up to 64)
+    int64_t rstride;             // elements per population row block (2 * 19 * pitch)
+    void *f[2];                  // ping-pong population buffers
+    double *rho;                 // [nz][ny][2][pitch] densities of the current pull
+    double tau[2], itau[2];      // relaxation times and their reciprocals
+    double G;                    // Shan-Chen coupling
+    double g[2][3];              // body acceleration per component
+};
+
+struct Fields3 {
+    double *rhoA, *rhoB, *ux, *uy, *uz;   // [nz][ny][nx], any may be null
+};
+
+// Pull the 38 populations of site (x, y, z) from the post-collision buffer.
+template <int ST, int BCY>
+__device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int y, int x, double (&f)[2][NQ3])
+{
+    using T = typename Tr<ST>::T;
+    const int64_t row_bytes = L.rstride * (int64_t)sizeof(T);
+    const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
+    const unsigned ss = (unsigned)NQ3 * is;
+    const unsigned oc = (unsigned)x * (unsigned)sizeof(T);
+    const unsigned om = (unsigned)(x == 0 ? L.nx - 1 : x - 1) * (unsigned)sizeof(T);    // source of c_x = +1
+    const unsigned op = (unsigned)(x == L.nx - 1 ? 0 : x + 1) * (unsigned)sizeof(T);    // source of c_x = -1
+#pragma unroll
+    for (int i = 0; i < NQ3; ++i) {
+        int ys = y - c3y(i), zs = z - c3z(i);
+        unsigned col = c3x(i) > 0 ? om : (c3x(i) < 0 ? op : oc);
+        int seg = i;
+        if (BCY == lbk::BC_PERIODIC) {
+            if (ys < 0) ys += L.ny;
+            if (ys >= L.ny) ys -= L.ny;
+        } else if (ys < 0 || ys >= L.ny) {
+            // halfway bounce-back: the reversed population of the site itself
+            ys = y;
+            zs = z;
+            col = oc;
+            seg = opp3(i);
+        }
+        if (zs < 0) zs += L.nz;
+        if (zs >= L.nz) zs -= L.nz;
+        const rsrc_t r = row_rsrc(src, zs * L.ny + ys, row_bytes);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            f[s][i] = (double)bload<T>(r, col, (unsigned)s * ss + (unsigned)seg * is);
+    }
+}
+
+// Eq. 1: rho_s = sum_i f_i in index order.
+__device__ __forceinline__ double density3(const double (&f)[NQ3])
+{
+    double r = f[0];
+#pragma unroll
+    for (int i = 1; i < NQ3; ++i) r += f[i];
+    return r;
+}
+
+// j_s = sum_i f_i c_i in index order (terms with a zero component add nothing).
+__device__ __forceinline__ void momentum3(const double (&f)[NQ3], double &jx, double &jy, double &jz)
+{
+    double mx = 0.0, my = 0.0, mz = 0.0;
+    bool fx = true, fy = true, fz = true;
+#pragma unroll
+    for (int i = 1; i < NQ3; ++i) {
+        if (c3x(i) != 0) {
+            mx = fx ? (c3x(i) > 0 ? f[i] : -f[i]) : (c3x(i) > 0 ? mx + f[i] : mx - f[i]);
+            fx = false;
+        }
+        if (c3y(i) != 0) {
+            my = fy ? (c3y(i) > 0 ? f[i] : -f[i]) : (c3y(i) > 0 ? my + f[i] : my - f[i]);
+            fy = false;
+        }
+        if (c3z(i) != 0) {
+            mz = fz ? (c3z(i) > 0 ? f[i] : -f[i]) : (c3z(i) > 0 ? mz + f[i] : mz - f[i]);
+            fz = false;
+        }
+    }
+    jx = mx;
+    jy = my;
+    jz = mz;
+}
+
+// Density of component s at the neighbour x + c_i: x and z wrap; y wraps
+// (periodic) or, beyond a wall, takes the wall row (mirror).
+template <int BCY>
+__device__ __forceinline__ double rho_nb(const Lat3 &L, int z, int y, int x, int s, int i)
+{
+    int xn = x + c3x(i), yn = y + c3y(i), zn = z + c3z(i);
+    if (xn < 0) xn += L.nx;
+    if (xn >= L.nx) xn -= L.nx;
+    if (zn < 0) zn += L.nz;
+    if (zn >= L.nz) zn -= L.nz;
+    if (BCY == lbk::BC_PERIODIC) {
+        if (yn < 0) yn += L.ny;
+        if (yn >= L.ny) yn -= L.ny;
+    } else {
+        if (yn < 0) yn = 0;
+        if (yn >= L.ny) yn = L.ny - 1;
+    }
+    return L.rho[((int64_t)(zn * L.ny + yn) * 2 + s) * L.pitch + xn];
+}
+
+// Eq. 5 sum S = sum_i w_i rho(x + c_i) c_i of component s, in index order
+// (each component sums only the links with a nonzero entry).
+template <int BCY>
+__device__ __forceinline__ void sc_sum3(const Lat3 &L, int z, int y, int x, int s, double &Sx, double &Sy, double &Sz)
+{
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    bool fx = true, fy = true, fz = true;
+#pragma unroll
+    for (int i = 1; i < NQ3; ++i) {
+        const double wp = w3(i) * rho_nb<BCY>(L, z, y, x, s, i);
+        if (c3x(i) != 0) {
+            sx = fx ? (c3x(i) > 0 ? wp : -wp) : (c3x(i) > 0 ? sx + wp : sx - wp);
+            fx = false;
+        }
+        if (c3y(i) != 0) {
+            sy = fy ? (c3y(i) > 0 ? wp : -wp) : (c3y(i) > 0 ? sy + wp : sy - wp);
+            fy = false;
+        }
+        if (c3z(i) != 0) {
+            sz = fz ? (c3z(i) > 0 ? wp : -wp) : (c3z(i) > 0 ? sz + wp : sz - wp);
+            fz = false;
+        }
+    }
+    Sx = sx;
+    Sy = sy;
+    Sz = sz;
+}
+
+constexpr int WX = 64, WY = 4;   // threads per block: one wave per row segment, four rows
+
+template <int ST, int BCY>
+__global__ void __launch_bounds__(WX * WY) k3_density(Lat3 L, int cur)
+{
+    const int x = blockIdx.x * WX + threadIdx.x;
+    const int y = blockIdx.y * WY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= L.nx || y >= L.ny) return;
+    double f[2][NQ3];
+    pull3<ST, BCY>(L.f[cur], L, z, y, x, f);
+    const int64_t base = (int64_t)(z * L.ny + y) * 2 * L.pitch + x;
+    L.rho[base] = density3(f[0]);
+    L.rho[base + L.pitch] = density3(f[1]);
+}
+
+template <int ST, int BCY, bool FIELDS>
+__global__ void __launch_bounds__(WX * WY) k3_collide(Lat3 L, int cur, Fields3 fo)
+{
+    using T = typename Tr<ST>::T;
+    const int x = blockIdx.x * WX + threadIdx.x;
+    const int y = blockIdx.y * WY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= L.nx || y >= L.ny) return;
+    double f[2][NQ3];
+    pull3<ST, BCY>(L.f[cur], L, z, y, x, f);
+    double rho[2], jx[2], jy[2], jz[2], ax[2], ay[2], az[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rho[s] = density3(f[s]);
+        momentum3(f[s], jx[s], jy[s], jz[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        // a_s = -G S_sbar + g_s   (Eq. 5 with psi = rho, plus Eq. 7)
+        double Sx, Sy, Sz;
+        sc_sum3<BCY>(L, z, y, x, 1 - s, Sx, Sy, Sz);
+        ax[s] = -L.G * Sx + L.g[s][0];
+        ay[s] = -L.G * Sy + L.g[s][1];
+        az[s] = -L.G * Sz + L.g[s][2];
+    }
+    const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
+    if constexpr (FIELDS) {
+        const double Fx = rho[0] * ax[0] + rho[1] * ax[1];
+        const double Fy = rho[0] * ay[0] + rho[1] * ay[1];
+        const double Fz = rho[0] * az[0] + rho[1] * az[1];
+        const double rt = rho[0] + rho[1];
+        if (fo.rhoA) fo.rhoA[k] = rho[0];
+        if (fo.rhoB) fo.rhoB[k] = rho[1];
+        if (fo.ux) fo.ux[k] = (jx[0] + jx[1] + 0.5 * Fx) / rt;
+        if (fo.uy) fo.uy[k] = (jy[0] + jy[1] + 0.5 * Fy) / rt;
+        if (fo.uz) fo.uz[k] = (jz[0] + jz[1] + 0.5 * Fz) / rt;
+    } else {
+        // Eq. 1: velocity weighted by 1/tau_s
+        const double den = rho[0] * L.itau[0] + rho[1] * L.itau[1];
+        const double ux = (jx[0] * L.itau[0] + jx[1] * L.itau[1]) / den;
+        const double uy = (jy[0] * L.itau[0] + jy[1] * L.itau[1]) / den;
+        const double uz = (jz[0] * L.itau[0] + jz[1] * L.itau[1]) / den;
+        const rsrc_t wr = row_rsrc(L.f[cur ^ 1], z * L.ny + y, L.rstride * (int64_t)sizeof(T));
+        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+        const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            // Eq. 3 at the shifted velocity u + tau_s a_s
+            const double vx = ux + L.tau[s] * ax[s];
+            const double vy = uy + L.tau[s] * ay[s];
+            const double vz = uz + L.tau[s] * az[s];
+            const double vv = vx * vx + vy * vy + vz * vz;
+            const double om = L.itau[s];
+#pragma unroll
+            for (int i = 0; i < NQ3; ++i) {
+                // c_i . v, summed over the nonzero components in the order x, y, z
+                double cv = 0.0;
+                bool first = true;
+                if (c3x(i) != 0) {
+                    cv = c3x(i) > 0 ? vx : -vx;
+                    first = false;
+                }
+                if (c3y(i) != 0) {
+                    cv = first ? (c3y(i) > 0 ? vy : -vy) : (c3y(i) > 0 ? cv + vy : cv - vy);
+                    first = false;
+                }
+                if (c3z(i) != 0) cv = first ? (c3z(i) > 0 ? vz : -vz) : (c3z(i) > 0 ? cv + vz : cv - vz);
+                const double feq = rho[s] * w3(i) * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+                const double post = f[s][i] - om * (f[s][i] - feq);   // Eq. 2
+                bstore<LBK_NT_STORE ? lbk::CPOL_NT : 0>((T)post, wr, ox, (unsigned)(s * NQ3 + i) * is);
+            }
+        }
+    }
+}
+
+// Canonical f(t) [s][i][z][y][x] (or the rest equilibrium w_i rho_s of the
+// density fields when fcan is null) into the stored post-collision form:
+// f*_i(x) = f_i(x + c_i), or f_opp(i)(x) where x + c_i lies beyond a wall.
+template <int ST, int BCY>
+__global__ void __launch_bounds__(WX * WY)
+k3_scatter(Lat3 L, int cur, const double *__restrict__ fcan, const double *__restrict__ rhoA,
+           const double *__restrict__ rhoB)
+{
+    using T = typename Tr<ST>::T;
+    const int x = blockIdx.x * WX + threadIdx.x;
+    const int y = blockIdx.y * WY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= L.nx || y >= L.ny) return;
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    const rsrc_t wr = row_rsrc(L.f[cur], z * L.ny + y, L.rstride * (int64_t)sizeof(T));
+    const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < NQ3; ++i) {
+        int xs = x + c3x(i), ys = y + c3y(i), zs = z + c3z(i), src_i = i;
+        if (xs < 0) xs += L.nx;
+        if (xs >= L.nx) xs -= L.nx;
+        if (zs < 0) zs += L.nz;
+        if (zs >= L.nz) zs -= L.nz;
+        if (BCY == lbk::BC_PERIODIC) {
+            if (ys < 0) ys += L.ny;
+            if (ys >= L.ny) ys -= L.ny;
+        } else if (ys < 0 || ys >= L.ny) {
+            xs = x;
+            ys = y;
+            zs = z;
+            src_i = opp3(i);
+        }
+        const int64_t k = ((int64_t)zs * L.ny + ys) * L.nx + xs;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double v = fcan ? fcan[(int64_t)(s * NQ3 + src_i) * n + k] : w3(src_i) * (s == 0 ? rhoA[k] : rhoB[k]);
+            bstore<0>((T)v, wr, (unsigned)x * (unsigned)sizeof(T), (unsigned)(s * NQ3 + i) * is);
+        }
+    }
+}
+
+// Stored form -> canonical f(t) (the pull).
+template <int ST, int BCY>
+__global__ void __launch_bounds__(WX * WY) k3_gather(Lat3 L, int cur, double *__restrict__ fcan)
+{
+    const int x = blockIdx.x * WX + threadIdx.x;
+    const int y = blockIdx.y * WY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= L.nx || y >= L.ny) return;
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    double f[2][NQ3];
+    pull3<ST, BCY>(L.f[cur], L, z, y, x, f);
+    const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < NQ3; ++i) fcan[(int64_t)(s * NQ3 + i) * n + k] = f[s][i];
+}
+
+// Per-row partial sums of the fields: mass_A, mass_B, E_k (trimmed rows
+// only), max |u|^2, count of non-finite values.  One block per (z, y) row.
+constexpr int RED3_NQ = 5;
+constexpr int RED3_THREADS = 256;
+
+__global__ void __launch_bounds__(RED3_THREADS)
+k3_reduce_rows(const double *__restrict__ rA, const double *__restrict__ rB, const double *__restrict__ ux,
+               const double *__restrict__ uy, const double *__restrict__ uz, int nx, int ny, int trim,
+               double *__restrict__ part)
+{
+    __shared__ double sh[RED3_NQ][RED3_THREADS];
+    const int row = blockIdx.x;
+    const int y = row % ny;
+    const bool in_d = y >= trim && y < ny - trim;
+    double acc[RED3_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int x = threadIdx.x; x < nx; x += RED3_THREADS) {
+        const int64_t k = (int64_t)row * nx + x;
+        const double a = rA[k], b = rB[k], u = ux[k], v = uy[k], w = uz[k];
+        const double u2 = u * u + v * v + w * w;
+        acc[0] += a;
+        acc[1] += b;
+        if (in_d) acc[2] += 0.5 * (a + b) * u2;
+        acc[3] = fmax(acc[3], u2);
+        const bool fin = isfinite(a) && isfinite(b) && isfinite(u) && isfinite(v) && isfinite(w);
+        acc[4] += fin ? 0.0 : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RED3_NQ; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = RED3_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int q = 0; q < RED3_NQ; ++q)
+                sh[q][threadIdx.x] = q == 3 ? fmax(sh[q][threadIdx.x], sh[q][threadIdx.x + h])
+                                            : sh[q][threadIdx.x] + sh[q][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < RED3_NQ) part[(int64_t)row * RED3_NQ + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(RED3_THREADS) k3_reduce_final(const double *__restrict__ part, int rows, double *out)
+{
+    __shared__ double sh[RED3_NQ][RED3_THREADS];
+    double acc[RED3_NQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int r = threadIdx.x; r < rows; r += RED3_THREADS) {
+#pragma unroll
+        for (int q = 0; q < RED3_NQ; ++q) {
+            const double v = part[(int64_t)r * RED3_NQ + q];
+            acc[q] = q == 3 ? fmax(acc[q], v) : acc[q] + v;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RED3_NQ; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = RED3_THREADS / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int q = 0; q < RED3_NQ; ++q)
+                sh[q][threadIdx.x] = q == 3 ? fmax(sh[q][threadIdx.x], sh[q][threadIdx.x + h])
+                                            : sh[q][threadIdx.x] + sh[q][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < RED3_NQ) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+}  // namespace lbk3

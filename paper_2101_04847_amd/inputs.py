@@ -130,3 +130,31 @@ def ensemble_16():
             members.append(Workload(nx, ny, G=G, seed=seed, name=f"ens-{nx}x{ny}-s{seed}"))
             seed += 1
     return members
+
+
+def rt3d_densities(nx: int, ny: int, nz: int, seed: int, n_modes: int = 8, amp_max: float = 0.5):
+    """3D Rayleigh-Taylor set-up for the D3Q19 extension: heavy A on top of
+    light B with the interface y_int(x, z) = (ny - 1)/2 + sum over random
+    modes (m, l) of a cos(2 pi (m x / nx + l z / nz) + theta), m, l in
+    1..n_modes, a ~ U[0, amp_max), theta ~ U[0, 2 pi); densities as in 2D.
+    Arrays [nz][ny][nx]."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(1, n_modes + 1, size=n_modes)
+    l = rng.integers(1, n_modes + 1, size=n_modes)
+    a = rng.uniform(0.0, amp_max, size=n_modes)
+    th = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    z = np.arange(nz, dtype=np.float64)[:, None]
+    h = np.full((nz, nx), 0.5 * (ny - 1))
+    for k in range(n_modes):
+        h += a[k] * np.cos(2.0 * np.pi * (m[k] * x / nx + l[k] * z / nz) + th[k])
+    y = np.arange(ny, dtype=np.float64)[None, :, None]
+    s = 0.5 * (1.0 + np.tanh((y - h[:, None, :]) / WIDTH))
+    rho_a = TRACE + (HEAVY_A - TRACE) * s
+    rho_b = TRACE + (HEAVY_B - TRACE) * (1.0 - s)
+    return np.ascontiguousarray(rho_a), np.ascontiguousarray(rho_b)
+
+
+# The 3D workload of the D3Q19 extension: 384^3 sites (about the site count
+# of the 10000 x 5000 lattice), tau = 1, G = 1.5, g = 1e-5, walls in y.
+D3_384 = dict(nx=384, ny=384, nz=384, seed=4, G=1.5, g=1e-5, tau=1.0, name="rt3d-384^3-8modes")

@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for rel in ("paper_2101_04847_amd/csrc/lb_kernels.hpp", "paper_2101_04847_amd/csrc/lb.hip",
-                "paper_2101_04847_amd/csrc/lb_internal.hpp"):
+                "paper_2101_04847_amd/csrc/lb_internal.hpp", "paper_2101_04847_amd/csrc/lb_memory.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

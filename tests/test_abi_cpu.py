@@ -39,9 +39,10 @@ def test_header_constants_match_binding(lb):
     assert (consts["LB_F64"], consts["LB_F32"], consts["LB_F16S"], consts["LB_BF16S"]) == (0, 1, 2, 3)
     assert (consts["LB_FORCE_SHIFT"], consts["LB_FORCE_GUO"]) == (0, 1)
     assert (consts["LB_WALLS"], consts["LB_PERIODIC_Y"]) == (0, 1)
+    assert (consts["LB_PSI_MIRROR"], consts["LB_PSI_ZERO"]) == (lb.PSI_MIRROR, lb.PSI_ZERO) == (0, 1)
     assert consts["LB_MAX_MEMBERS"] == lb.MAX_MEMBERS
     # struct sizes the binding assumes
-    assert ctypes.sizeof(lb.LbMember) == 4 * 2 + 8 * 2 + 8 + 8 * 4 + 8 * 2 + 8 * 2
+    assert ctypes.sizeof(lb.LbMember) == 4 * 2 + 8 * 2 + 8 + 8 * 4 + 8 * 2 + 8 * 2 + 8 * 2 + 4 + 4
     assert ctypes.sizeof(lb.LbDiag) == 8 + 16 + 5 * 8 + 8
     assert ctypes.sizeof(lb.LbConfig) == 4 + 4 + 8 + 8 * 4
     assert ctypes.sizeof(lb.LbBudget) == 8 + 6 * 8
@@ -88,6 +89,8 @@ def test_config_validation(lb, kw, msg):
     (dict(nx=2), "nx"),
     (dict(ny=20), "trimming"),
     (dict(G=float("inf")), "G_AB"),
+    (dict(G_wall=(0.1, float("nan"))), "G_wall"),
+    (dict(wall_psi=2), "wall_psi"),
 ])
 def test_member_validation(lb, mkw, msg):
     nx = mkw.pop("nx", 32)
@@ -146,13 +149,70 @@ def test_oracle_is_not_imported_by_the_product(lb):
                 assert "orc_" not in text, fn
 
 
+@pytest.mark.parametrize("header,struct", [("lb.h", "lb_config"), ("lb3.h", "lb3_config")])
 @pytest.mark.parametrize("lang", ["c", "c++"])
-def test_header_compiles_cleanly(lang, tmp_path):
-    """include/lb.h is self-contained and warning-free as C and C++."""
+def test_header_compiles_cleanly(lang, header, struct, tmp_path):
+    """include/lb.h and include/lb3.h are self-contained and warning-free as
+    C and C++."""
     import subprocess
     src = tmp_path / ("t.c" if lang == "c" else "t.cpp")
-    src.write_text('#include "lb.h"\nint main(void) { return (int)sizeof(lb_config); }\n')
+    src.write_text(f'#include "{header}"\nint main(void) {{ return (int)sizeof({struct}); }}\n')
     cc = "gcc" if lang == "c" else "g++"
     r = subprocess.run([cc, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"),
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+# --- the 3D (D3Q19) entry points ---------------------------------------------
+
+@pytest.fixture(scope="module")
+def lb3(lb):
+    from paper_2101_04847_amd import lb3 as mod
+    return mod
+
+
+def test_lb3_declared_symbols_are_exported(lb3):
+    src = open(os.path.join(ROOT, "include", "lb3.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(lb3_[a-z_]+)\s*\(", src)))
+    assert len(names) >= 9
+    assert sorted(lb3.EXPORTS3) == names
+    for n in names:
+        assert hasattr(lb3._lib, n), n
+    assert ctypes.sizeof(lb3.Lb3Config) == 6 * 4 + 2 * 8 + 8 + 6 * 8 + 2 * 8
+    assert ctypes.sizeof(lb3.Lb3Diag) == 8 + 2 * 8 + 8 + 8 + 4 + 4
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(storage=2), "storage"),
+    (dict(nz=2), "nz"),
+    (dict(diag_trim=5), "diag_trim"),
+    (dict(tau=(0.5, 1.0)), "tau"),
+    (dict(G=float("nan")), "G_AB"),
+    (dict(bc_y=3), "bc_y"),
+    (dict(nx=8_000_000, ny=3, nz=3), "row block"),
+])
+def test_lb3_config_validation(lb, lb3, kw, msg):
+    nx, ny, nz = kw.pop("nx", 8), kw.pop("ny", 10), kw.pop("nz", 6)
+    r = np.ones((nz, ny, nx))
+    c, _k = lb3.make_config3(nx, ny, nz, r, r, **kw)
+    assert lb3._lib.lb3_workspace_bytes(ctypes.byref(c)) == 0
+    assert msg in lb.last_error()
+
+
+def test_lb3_workspace_and_bogus_handle(lb, lb3):
+    r = np.ones((6, 10, 100))
+    c64, _a = lb3.make_config3(100, 10, 6, r, r, storage=lb.F64)
+    c32, _b = lb3.make_config3(100, 10, 6, r, r, storage=lb.F32)
+    pops = 2 * 19 * 10 * 6 * 128
+    b64 = lb3._lib.lb3_workspace_bytes(ctypes.byref(c64))
+    b32 = lb3._lib.lb3_workspace_bytes(ctypes.byref(c32))
+    assert b64 - b32 == 2 * pops * 4
+    assert b64 >= 2 * pops * 8 + 5 * 100 * 10 * 6 * 8
+    bogus = ctypes.c_void_p(0x1234)
+    assert lb3._lib.lb3_step(bogus, 1) == lb.LB_ESTATE
+    assert lb3._lib.lb3_time(bogus) == -1
+    assert lb3._lib.lb3_destroy(bogus) == lb.LB_ESTATE
+    d = lb3.Lb3Diag()
+    assert lb3._lib.lb3_diagnostics(bogus, ctypes.byref(d)) == lb.LB_ESTATE
+    assert lb3._lib.lb3_fields(bogus, None, None, None, None, None) == lb.LB_ESTATE
