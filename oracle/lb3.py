@@ -119,6 +119,14 @@ def run(p: Params3, f: np.ndarray, steps: int) -> np.ndarray:
     return out
 
 
+def run_inplace(p: Params3, f: np.ndarray, steps: int) -> None:
+    """Advance f (C-contiguous float64) by ``steps`` steps in place."""
+    assert f.dtype == np.float64 and f.flags.c_contiguous
+    pc = p.c()
+    if _load().orc3_run(ctypes.byref(pc), _ptr(f), int(steps)) != 0:
+        raise MemoryError("oracle 3D run: allocation failed")
+
+
 def macro(p: Params3, f: np.ndarray) -> dict:
     """rhoA, rhoB, hydrodynamic velocity (ux, uy, uz) and total force (Fx, Fy, Fz)."""
     f = np.ascontiguousarray(f, dtype=np.float64)

@@ -524,7 +524,7 @@ int32_t choose_tiles(lb_handle *h)
     int best_tx = c.tile_x != 0 ? c.tile_x : 128;
     std::vector<int> best_th(nm, c.tile_h > 0 ? c.tile_h : 16);
     if (c.tile_x == 0 && spp != 2) {
-        std::vector<int> heights = {16, 32, 64, 128};
+        std::vector<int> heights = {8, 12, 16, 32, 64, 128};
         if (c.tile_h > 0) heights = {c.tile_h};
         for (int tx : {64, 128, 256, 512}) {
             if (tx > 64 && tx / 2 >= max_nx) continue;
@@ -549,7 +549,7 @@ int32_t choose_tiles(lb_handle *h)
         std::vector<int> th2(nm, c.tile_h > 0 ? c.tile_h : 12);
         float best2 = 0.0f;
         if (c.tile_h == 0 || spp == 0) {
-            std::vector<int> heights = {8, 12, 16, 24};
+            std::vector<int> heights = {6, 8, 10, 12, 16, 24};
             if (c.tile_h > 0) heights = {c.tile_h};
             int32_t rc = search(heights, 12, [&](const std::vector<int> &thm, float &t) {
                 return time_shape2(h, thm, reps, t);

@@ -54,6 +54,8 @@ int32_t validate3(const lb3_config *c)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(c->g[s][a])) return fail(LB_EINVAL, "g[%d][%d] is not finite", s, a);
     if (!c->rhoA0 || !c->rhoB0) return fail(LB_EINVAL, "initial densities are NULL");
+    if (c->two_pass != 0 && c->two_pass != 1) return fail(LB_EINVAL, "two_pass = %d must be 0 or 1", c->two_pass);
+    if (c->reserved != 0) return fail(LB_EINVAL, "reserved = %d must be 0", c->reserved);
     return LB_OK;
 }
 
@@ -108,6 +110,19 @@ dim3 grid3(const lb3_handle *h)
 {
     return dim3((unsigned)((h->cfg.nx + WX - 1) / WX), (unsigned)((h->cfg.ny + WY - 1) / WY), (unsigned)h->cfg.nz);
 }
+
+constexpr int FUSED_NZB = 32;   // planes per band of the fused pass
+
+dim3 grid_fused(const lb3_handle *h)
+{
+    return dim3((unsigned)((h->cfg.nx + FX - 3) / (FX - 2)), (unsigned)((h->cfg.ny + FY - 3) / (FY - 2)),
+                (unsigned)((h->cfg.nz + FUSED_NZB - 1) / FUSED_NZB));
+}
+
+using FusedFn = void (*)(Lat3, int, int);
+template <int ST>
+FusedFn fused_st(int bc) { return bc == LB_WALLS ? k3_fused<ST, lbk::BC_WALLS> : k3_fused<ST, lbk::BC_PERIODIC>; }
+FusedFn pick_fused(int st, int bc) { return st == LB_F64 ? fused_st<lbk::ST_F64>(bc) : fused_st<lbk::ST_F32>(bc); }
 
 using DensFn = void (*)(Lat3, int);
 using CollFn = void (*)(Lat3, int, Fields3);
@@ -216,14 +231,24 @@ int32_t lb3_step(lb3_handle *h, int64_t n)
 {
     if (!live3(h)) return fail(LB_ESTATE, "handle is not live");
     if (n < 0) return fail(LB_EINVAL, "n = %lld is negative", (long long)n);
-    const DensFn fd = pick_dens(h->cfg.storage, h->cfg.bc_y);
-    const CollFn fc = pick_coll(h->cfg.storage, h->cfg.bc_y, false);
-    const dim3 g = grid3(h);
-    for (int64_t k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(fd, g, dim3(WX, WY), 0, h->stream, h->L, h->cur);
-        hipLaunchKernelGGL(fc, g, dim3(WX, WY), 0, h->stream, h->L, h->cur, Fields3{});
-        h->cur ^= 1;
-        h->t += 1;
+    if (h->cfg.two_pass) {
+        const DensFn fd = pick_dens(h->cfg.storage, h->cfg.bc_y);
+        const CollFn fc = pick_coll(h->cfg.storage, h->cfg.bc_y, false);
+        const dim3 g = grid3(h);
+        for (int64_t k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(fd, g, dim3(WX, WY), 0, h->stream, h->L, h->cur);
+            hipLaunchKernelGGL(fc, g, dim3(WX, WY), 0, h->stream, h->L, h->cur, Fields3{});
+            h->cur ^= 1;
+            h->t += 1;
+        }
+    } else {
+        const FusedFn ff = pick_fused(h->cfg.storage, h->cfg.bc_y);
+        const dim3 g = grid_fused(h);
+        for (int64_t k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(ff, g, dim3(FX, FY), 0, h->stream, h->L, h->cur, FUSED_NZB);
+            h->cur ^= 1;
+            h->t += 1;
+        }
     }
     HIP_TRY(hipGetLastError());
     return LB_OK;

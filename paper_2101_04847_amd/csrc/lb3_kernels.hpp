@@ -155,16 +155,17 @@ __device__ __forceinline__ double rho_nb(const Lat3 &L, int z, int y, int x, int
     return L.rho[((int64_t)(zn * L.ny + yn) * 2 + s) * L.pitch + xn];
 }
 
-// Eq. 5 sum S = sum_i w_i rho(x + c_i) c_i of component s, in index order
-// (each component sums only the links with a nonzero entry).
-template <int BCY>
-__device__ __forceinline__ void sc_sum3(const Lat3 &L, int z, int y, int x, int s, double &Sx, double &Sy, double &Sz)
+// Eq. 5 sum S = sum_i w_i rho(x + c_i) c_i of one component, in index order
+// (each component sums only the links with a nonzero entry); nb(i) is the
+// component's density at x + c_i.
+template <class NB>
+__device__ __forceinline__ void sc_sum3_nb(NB &&nb, double (&S)[3])
 {
     double sx = 0.0, sy = 0.0, sz = 0.0;
     bool fx = true, fy = true, fz = true;
 #pragma unroll
     for (int i = 1; i < NQ3; ++i) {
-        const double wp = w3(i) * rho_nb<BCY>(L, z, y, x, s, i);
+        const double wp = w3(i) * nb(i);
         if (c3x(i) != 0) {
             sx = fx ? (c3x(i) > 0 ? wp : -wp) : (c3x(i) > 0 ? sx + wp : sx - wp);
             fx = false;
@@ -178,9 +179,66 @@ __device__ __forceinline__ void sc_sum3(const Lat3 &L, int z, int y, int x, int 
             fz = false;
         }
     }
-    Sx = sx;
-    Sy = sy;
-    Sz = sz;
+    S[0] = sx;
+    S[1] = sy;
+    S[2] = sz;
+}
+
+// Shan-Chen + body acceleration a_s = -G S_sbar + g_s (Eq. 5 with psi = rho,
+// plus Eq. 7) of both components from the sums S[s] of each component.
+__device__ __forceinline__ void accel3(const Lat3 &L, const double (&S)[2][3], double (&a)[2][3])
+{
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a[s][d] = -L.G * S[1 - s][d] + L.g[s][d];
+}
+
+// Collision of one site (Eq. 1-3 and the BGK relaxation of Eq. 2, velocity
+// shift) and the store of f*(t) at the site into buffer cur ^ 1.
+template <int ST>
+__device__ __forceinline__ void collide_store3(const Lat3 &L, const double (&f)[2][NQ3], const double (&rho)[2],
+                                               const double (&a)[2][3], int cur, int z, int y, int x)
+{
+    using T = typename Tr<ST>::T;
+    double j[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) momentum3(f[s], j[s][0], j[s][1], j[s][2]);
+    // Eq. 1: velocity weighted by 1/tau_s
+    const double den = rho[0] * L.itau[0] + rho[1] * L.itau[1];
+    const double ux = (j[0][0] * L.itau[0] + j[1][0] * L.itau[1]) / den;
+    const double uy = (j[0][1] * L.itau[0] + j[1][1] * L.itau[1]) / den;
+    const double uz = (j[0][2] * L.itau[0] + j[1][2] * L.itau[1]) / den;
+    const rsrc_t wr = row_rsrc(L.f[cur ^ 1], z * L.ny + y, L.rstride * (int64_t)sizeof(T));
+    const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
+    const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        // Eq. 3 at the shifted velocity u + tau_s a_s
+        const double vx = ux + L.tau[s] * a[s][0];
+        const double vy = uy + L.tau[s] * a[s][1];
+        const double vz = uz + L.tau[s] * a[s][2];
+        const double vv = vx * vx + vy * vy + vz * vz;
+        const double om = L.itau[s];
+#pragma unroll
+        for (int i = 0; i < NQ3; ++i) {
+            // c_i . v, summed over the nonzero components in the order x, y, z
+            double cv = 0.0;
+            bool first = true;
+            if (c3x(i) != 0) {
+                cv = c3x(i) > 0 ? vx : -vx;
+                first = false;
+            }
+            if (c3y(i) != 0) {
+                cv = first ? (c3y(i) > 0 ? vy : -vy) : (c3y(i) > 0 ? cv + vy : cv - vy);
+                first = false;
+            }
+            if (c3z(i) != 0) cv = first ? (c3z(i) > 0 ? vz : -vz) : (c3z(i) > 0 ? cv + vz : cv - vz);
+            const double feq = rho[s] * w3(i) * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
+            const double post = f[s][i] - om * (f[s][i] - feq);   // Eq. 2
+            bstore<LBK_NT_STORE ? lbk::CPOL_NT : 0>((T)post, wr, ox, (unsigned)(s * NQ3 + i) * is);
+        }
+    }
 }
 
 constexpr int WX = 64, WY = 4;   // threads per block: one wave per row segment, four rows
@@ -202,74 +260,98 @@ __global__ void __launch_bounds__(WX * WY) k3_density(Lat3 L, int cur)
 template <int ST, int BCY, bool FIELDS>
 __global__ void __launch_bounds__(WX * WY) k3_collide(Lat3 L, int cur, Fields3 fo)
 {
-    using T = typename Tr<ST>::T;
     const int x = blockIdx.x * WX + threadIdx.x;
     const int y = blockIdx.y * WY + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= L.nx || y >= L.ny) return;
     double f[2][NQ3];
     pull3<ST, BCY>(L.f[cur], L, z, y, x, f);
-    double rho[2], jx[2], jy[2], jz[2], ax[2], ay[2], az[2];
+    double rho[2], S[2][3], a[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         rho[s] = density3(f[s]);
-        momentum3(f[s], jx[s], jy[s], jz[s]);
+        sc_sum3_nb([&](int i) { return rho_nb<BCY>(L, z, y, x, s, i); }, S[s]);
     }
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        // a_s = -G S_sbar + g_s   (Eq. 5 with psi = rho, plus Eq. 7)
-        double Sx, Sy, Sz;
-        sc_sum3<BCY>(L, z, y, x, 1 - s, Sx, Sy, Sz);
-        ax[s] = -L.G * Sx + L.g[s][0];
-        ay[s] = -L.G * Sy + L.g[s][1];
-        az[s] = -L.G * Sz + L.g[s][2];
-    }
-    const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
+    accel3(L, S, a);
     if constexpr (FIELDS) {
-        const double Fx = rho[0] * ax[0] + rho[1] * ax[1];
-        const double Fy = rho[0] * ay[0] + rho[1] * ay[1];
-        const double Fz = rho[0] * az[0] + rho[1] * az[1];
+        double j[2][3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) momentum3(f[s], j[s][0], j[s][1], j[s][2]);
+        const double Fx = rho[0] * a[0][0] + rho[1] * a[1][0];
+        const double Fy = rho[0] * a[0][1] + rho[1] * a[1][1];
+        const double Fz = rho[0] * a[0][2] + rho[1] * a[1][2];
         const double rt = rho[0] + rho[1];
+        const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
         if (fo.rhoA) fo.rhoA[k] = rho[0];
         if (fo.rhoB) fo.rhoB[k] = rho[1];
-        if (fo.ux) fo.ux[k] = (jx[0] + jx[1] + 0.5 * Fx) / rt;
-        if (fo.uy) fo.uy[k] = (jy[0] + jy[1] + 0.5 * Fy) / rt;
-        if (fo.uz) fo.uz[k] = (jz[0] + jz[1] + 0.5 * Fz) / rt;
+        if (fo.ux) fo.ux[k] = (j[0][0] + j[1][0] + 0.5 * Fx) / rt;
+        if (fo.uy) fo.uy[k] = (j[0][1] + j[1][1] + 0.5 * Fy) / rt;
+        if (fo.uz) fo.uz[k] = (j[0][2] + j[1][2] + 0.5 * Fz) / rt;
     } else {
-        // Eq. 1: velocity weighted by 1/tau_s
-        const double den = rho[0] * L.itau[0] + rho[1] * L.itau[1];
-        const double ux = (jx[0] * L.itau[0] + jx[1] * L.itau[1]) / den;
-        const double uy = (jy[0] * L.itau[0] + jy[1] * L.itau[1]) / den;
-        const double uz = (jz[0] * L.itau[0] + jz[1] * L.itau[1]) / den;
-        const rsrc_t wr = row_rsrc(L.f[cur ^ 1], z * L.ny + y, L.rstride * (int64_t)sizeof(T));
-        const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
-        const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
+        collide_store3<ST>(L, f, rho, a, cur, z, y, x);
+    }
+}
+
+// The fused step: one pass per time step.  A block of FX x FY threads owns
+// an (FX - 2) x (FY - 2) tile of the x-y plane plus a one-site halo and
+// marches through a band of planes in z.  Per plane every thread pulls its
+// site of the plane ahead and puts its densities into a ring of four density
+// planes in LDS; after one barrier the interior threads pull their site of
+// the current plane again (read one plane earlier, so from cache), take the
+// 18 neighbour densities from the ring and collide.  HBM then carries each
+// population about once per read and once per write.
+constexpr int FX = 64, FY = 12;
+
+template <int ST, int BCY>
+__global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
+{
+    __shared__ double ring[4][2][FY][FX];
+    static_assert(FX == 64, "one wave per thread row: y is uniform across a wave");
+    const int lane = threadIdx.x;
+    const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int xu = blockIdx.x * (FX - 2) - 1 + lane;    // unwrapped column of this thread
+    const int yu = blockIdx.y * (FY - 2) - 1 + ty;      // unwrapped row (wave-uniform)
+    const int z0 = blockIdx.z * nzb;
+    const int nplanes = min(nzb, L.nz - z0);
+    // the site whose densities this thread provides: x wraps; beyond a wall
+    // the wall row (mirror), or y wraps
+    int xs = xu % L.nx;
+    if (xs < 0) xs += L.nx;
+    int ys = yu;
+    if (BCY == lbk::BC_PERIODIC) {
+        ys %= L.ny;
+        if (ys < 0) ys += L.ny;
+    } else {
+        ys = ys < 0 ? 0 : (ys >= L.ny ? L.ny - 1 : ys);
+    }
+    const bool interior = lane >= 1 && lane <= FX - 2 && ty >= 1 && ty <= FY - 2 && xu < L.nx && yu < L.ny;
+    const void *src = L.f[cur];
+    auto densities = [&](int zp, int slot) {
+        zp %= L.nz;
+        if (zp < 0) zp += L.nz;
+        double f[2][NQ3];
+        pull3<ST, BCY>(src, L, zp, ys, xs, f);
+        ring[slot][0][ty][lane] = density3(f[0]);
+        ring[slot][1][ty][lane] = density3(f[1]);
+    };
+    // ring slot of plane z0 + k is (k + 1) & 3
+    densities(z0 - 1, 0);
+    densities(z0, 1);
+    for (int k = 0; k < nplanes; ++k) {
+        const int z = z0 + k;
+        densities(z + 1, (k + 2) & 3);
+        __syncthreads();
+        if (interior) {
+            double f[2][NQ3];
+            pull3<ST, BCY>(src, L, z, yu, xu, f);
+            double rho[2], S[2][3], a[2][3];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            // Eq. 3 at the shifted velocity u + tau_s a_s
-            const double vx = ux + L.tau[s] * ax[s];
-            const double vy = uy + L.tau[s] * ay[s];
-            const double vz = uz + L.tau[s] * az[s];
-            const double vv = vx * vx + vy * vy + vz * vz;
-            const double om = L.itau[s];
-#pragma unroll
-            for (int i = 0; i < NQ3; ++i) {
-                // c_i . v, summed over the nonzero components in the order x, y, z
-                double cv = 0.0;
-                bool first = true;
-                if (c3x(i) != 0) {
-                    cv = c3x(i) > 0 ? vx : -vx;
-                    first = false;
-                }
-                if (c3y(i) != 0) {
-                    cv = first ? (c3y(i) > 0 ? vy : -vy) : (c3y(i) > 0 ? cv + vy : cv - vy);
-                    first = false;
-                }
-                if (c3z(i) != 0) cv = first ? (c3z(i) > 0 ? vz : -vz) : (c3z(i) > 0 ? cv + vz : cv - vz);
-                const double feq = rho[s] * w3(i) * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
-                const double post = f[s][i] - om * (f[s][i] - feq);   // Eq. 2
-                bstore<LBK_NT_STORE ? lbk::CPOL_NT : 0>((T)post, wr, ox, (unsigned)(s * NQ3 + i) * is);
+            for (int s = 0; s < 2; ++s) {
+                rho[s] = density3(f[s]);
+                sc_sum3_nb([&](int i) { return ring[(k + 1 + c3z(i)) & 3][s][ty + c3y(i)][lane + c3x(i)]; }, S[s]);
             }
+            accel3(L, S, a);
+            collide_store3<ST>(L, f, rho, a, cur, z, yu, xu);
         }
     }
 }

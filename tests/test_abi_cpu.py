@@ -179,7 +179,7 @@ def test_lb3_declared_symbols_are_exported(lb3):
     assert sorted(lb3.EXPORTS3) == names
     for n in names:
         assert hasattr(lb3._lib, n), n
-    assert ctypes.sizeof(lb3.Lb3Config) == 6 * 4 + 2 * 8 + 8 + 6 * 8 + 2 * 8
+    assert ctypes.sizeof(lb3.Lb3Config) == 8 * 4 + 2 * 8 + 8 + 6 * 8 + 2 * 8
     assert ctypes.sizeof(lb3.Lb3Diag) == 8 + 2 * 8 + 8 + 8 + 4 + 4
 
 

@@ -50,14 +50,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("two_pass", [False, True], ids=["fused", "two-pass"])
 @pytest.mark.parametrize("nx,ny,nz,per,tau,G,g", CASES)
-def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g):
-    _say("3d", nx, ny, nz, "periodic_y" if per else "walls", "tau", tau, "G", G, "g", g)
+def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g, two_pass):
+    _say("3d", nx, ny, nz, "periodic_y" if per else "walls", "tau", tau, "G", G, "g", g,
+         "two-pass" if two_pass else "fused")
     R = min(5.0, 0.35 * min(nx, ny, nz))
     rA, rB = _drop(nx, ny, nz, R)
     gg = ((2e-5, -g, 1e-5), (0.0, g, 0.0))
     lat = lb3.Lattice3(nx, ny, nz, rA, rB, tau=tau, G=G, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS,
-                       poison=True)
+                       poison=True, two_pass=two_pass)
     p = orc3.Params3(nx=nx, ny=ny, nz=nz, tau=tau, G=G, g=gg, periodic_y=per)
     f = orc3.fill_equilibrium(p, rA, rB)
     assert _rel(lat.get_populations().cpu().numpy(), f) <= TOL
@@ -75,6 +77,24 @@ def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g):
     for k in ("rhoA", "rhoB", "ux", "uy", "uz"):
         assert _rel(mg[k], mo[k]) <= TOL, k
     lat.close()
+
+
+@pytest.mark.parametrize("per", [False, True], ids=["walls", "periodic_y"])
+def test_3d_fused_equals_two_pass(lb3, per):
+    """The fused pass and the two-pass step agree bit for bit, over three
+    z bands (the last one ragged), tiles ragged in x and y."""
+    nx, ny, nz = 130, 45, 70
+    _say("3d fused vs two-pass", nx, ny, nz, "periodic_y" if per else "walls")
+    rA, rB = _drop(nx, ny, nz, R=9.0)
+    gg = ((0.0, -1e-4, 0.0), (0.0, 1e-4, 0.0))
+    kw = dict(tau=(1.0, 0.9), G=1.3, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS)
+    a = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=False, **kw)
+    b = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=True, **kw)
+    a.step(50)
+    b.step(50)
+    assert np.array_equal(a.get_populations().cpu().numpy(), b.get_populations().cpu().numpy())
+    a.close()
+    b.close()
 
 
 def test_3d_diagnostics_and_round_trip(lb3):
@@ -141,3 +161,32 @@ def test_3d_medium_lattice(lb3):
     for k in ("rhoA", "rhoB", "ux", "uy", "uz"):
         assert _rel(mg[k], mo[k]) <= TOL, k
     lat.close()
+
+
+@pytest.mark.timeout(900)
+def test_3d_bench_size_two_steps(lb3):
+    """The benchmark's 3D lattice (384^3, 8 random interface modes, walls,
+    tau = 1, G = 1.5, g = 1e-5): two steps, every density and velocity
+    against the oracle."""
+    import torch
+    from paper_2101_04847_amd import inputs
+    w = inputs.D3_384
+    nx, ny, nz = w["nx"], w["ny"], w["nz"]
+    _say("3d bench size", nx, ny, nz)
+    rA, rB = inputs.rt3d_densities(nx, ny, nz, w["seed"])
+    gg = ((0.0, -w["g"], 0.0), (0.0, w["g"], 0.0))
+    lat = lb3.Lattice3(nx, ny, nz, rA, rB, tau=(w["tau"], w["tau"]), G=w["G"], g=gg)
+    lat.step(2)
+    mg = {k: v.cpu().numpy() for k, v in lat.fields().items()}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    p = orc3.Params3(nx=nx, ny=ny, nz=nz, tau=(w["tau"], w["tau"]), G=w["G"], g=gg)
+    f = orc3.fill_equilibrium(p, rA, rB)
+    orc3.run_inplace(p, f, 2)
+    mo = orc3.macro(p, f)
+    del f
+    for k in ("rhoA", "rhoB", "ux", "uy", "uz"):
+        err = _rel(mg[k], mo[k])
+        print(f"[case] {k} max rel err {err:.3e}", flush=True)
+        assert err <= TOL, k
