@@ -9,7 +9,7 @@ import ctypes
 
 import numpy as np
 
-from .lb import F32, F64, LB_EINVAL, LBError, PERIODIC_Y, WALLS, _check, _lib
+from .lb import F32, F64, LB_EINVAL, LB_ENONFINITE, LBError, PERIODIC_Y, WALLS, _check, _lib
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _h = ctypes.c_void_p
@@ -113,14 +113,15 @@ class Lattice3:
         _check(_lib.lb3_fields(self._h, *[ctypes.c_void_p(out[k].data_ptr()) for k in keys]), "lb3_fields")
         return out
 
-    def diagnostics(self) -> dict:
+    def diagnostics(self, check_finite: bool = True) -> dict:
+        """Masses, E_k and max|u| (lb3_diag).  A non-finite state raises
+        unless check_finite is False (then "finite" is False)."""
         d = Lb3Diag()
         rc = _lib.lb3_diagnostics(self._h, ctypes.byref(d))
-        out = {"t": d.t, "mass_A": d.mass[0], "mass_B": d.mass[1], "Ek": d.Ek, "umax": d.umax,
-               "finite": bool(d.finite)}
-        if rc not in (0,) and d.finite:
-            _check(rc, "lb3_diagnostics")
-        return out
+        if rc != 0 and not (rc == LB_ENONFINITE and not check_finite):
+            raise LBError(rc, "lb3_diagnostics")
+        return {"t": d.t, "mass_A": d.mass[0], "mass_B": d.mass[1], "Ek": d.Ek, "umax": d.umax,
+                "finite": bool(d.finite)}
 
     def get_populations(self):
         import torch
