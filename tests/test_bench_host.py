@@ -1,0 +1,38 @@
+"""Host-side logic of bench.py (no GPU): the single-GPU refusal, the
+algorithmic byte counts behind the roofline figures, and the fraction of
+the HBM peak they imply."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_algorithmic_bytes_per_update():
+    # 2 components x 9 populations x (read + write) x element size
+    assert bench.BYTES_PER_LU == {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}
+    # 3D: 2 x 19 populations read and written once (fused), plus a second
+    # read and the density buffer in the two-pass step
+    assert bench.BYTES_PER_LU_3D_FUSED == {"f64": 608, "f32": 304}
+    assert bench.BYTES_PER_LU_3D == {"f64": 944, "f32": 488}
+
+
+def test_hbm_fraction():
+    # 10000 x 5000 FP64, two steps per pass at 1.7838 ms per step: 14.4 GB per 3.5676 ms
+    assert bench.hbm_frac("f64", 2, 1.7838, 5e7) == pytest.approx(14.4e9 / 3.5676e-3 / 8e12, abs=1e-4)
+    assert bench.hbm_frac("f64", 1, 2.7186, 5e7) == pytest.approx(0.6621, abs=1e-4)
+
+
+def test_traffic_record_missing_is_null():
+    assert bench.measured_traffic("step2", "f64", 123, 45) is None

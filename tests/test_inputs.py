@@ -37,3 +37,15 @@ def test_profile_densities_follow_the_profile():
     # beyond the profile the end values hold
     assert a[0, 0] == pa[0] and a[-1, 2] == pa[-1]
     assert np.allclose(a + b, 1.1)
+
+
+def test_rt3d_densities_recipe():
+    a, b = inputs.rt3d_densities(40, 30, 20, 4)
+    a2, _ = inputs.rt3d_densities(40, 30, 20, 4)
+    assert a.shape == (20, 30, 40) and a.flags.c_contiguous and np.array_equal(a, a2)
+    assert a.min() >= inputs.TRACE and a.max() <= inputs.HEAVY_A
+    # heavy A on top in every column, light B below
+    assert a[:, -1, :].min() > 1.0 and b[:, 0, :].min() > 0.9
+    # the interface is perturbed along both x and z
+    mid = a[:, 15, :]
+    assert np.ptp(mid, axis=1).max() > 1e-3 and np.ptp(mid, axis=0).max() > 1e-3
