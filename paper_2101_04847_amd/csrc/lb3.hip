@@ -1,6 +1,6 @@
 // Host runtime of the 3D (D3Q19) entry points declared in include/lb3.h:
-// validation, workspace layout, initial state, the two passes per step, the
-// field pass, reductions and state conversion.
+// validation, workspace layout, initial state, the step (one fused pass, or
+// two passes), the field pass, reductions and state conversion.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

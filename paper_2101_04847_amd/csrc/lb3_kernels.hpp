@@ -4,15 +4,20 @@
 // Storage: two buffers of row blocks [z][y][s][i][pitch] (the 38 row
 // segments of one lattice row adjacent, x fastest) holding post-collision
 // populations; f(t) is pulled: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) where
-// x - c_i lies beyond a y wall.  A step is two HBM-bound passes with one
-// thread per site and one 64-lane wave per row segment:
-//   k3_density   pulls f(t) and writes rho_A, rho_B ([z][y][2][pitch], FP64);
-//   k3_collide   pulls f(t) again, reads the 18 neighbour densities of the
-//                other component (cache-resident: 16 B per site), forms the
-//                Shan-Chen + body acceleration, the 1/tau-weighted velocity,
-//                the shifted equilibrium and the BGK relaxation, and stores
-//                f*(t) at the site; with FIELDS it writes rho_A, rho_B and the
-//                hydrodynamic velocity instead.
+// x - c_i lies beyond a y wall.  Two ways to run a step, both HBM-bound:
+//   k3_fused     one pass: a block owns a tile of the x-y plane and marches
+//                through a band of planes in z, keeping the densities of four
+//                planes in an LDS ring, so each population crosses HBM about
+//                once per read and once per write;
+//   k3_density + k3_collide
+//                two passes with one thread per site: the densities go to a
+//                [z][y][2][pitch] FP64 buffer, then the populations are pulled
+//                again, the 18 neighbour densities of the other component read
+//                (cache-resident: 16 B per site), and the Shan-Chen + body
+//                acceleration, the 1/tau-weighted velocity, the shifted
+//                equilibrium and the BGK relaxation applied; with FIELDS
+//                k3_collide writes rho_A, rho_B and the hydrodynamic velocity
+//                instead (the field pass).
 // All arithmetic is FP64 in both storage modes, every expression in the
 // order of its definition (sums over i in index order, no contraction), so
 // the FP64 mode is reproducible bit for bit by a plain implementation.
