@@ -41,8 +41,9 @@ typedef struct lb3_config {
     int32_t storage;         /* LB_F64 or LB_F32 (the arithmetic is FP64 in both) */
     int32_t diag_trim;       /* rows dropped next to each wall for the E_k average of
                                 lb3_diagnostics (>= 0, ny > 2 * diag_trim) */
-    int32_t two_pass;        /* 0: one fused pass per step (default); 1: two passes
-                                (densities, then force and collision); bit for bit
+    int32_t fused;           /* 0 (default): two passes per step (densities, then
+                                force and collision); 1: one fused pass (a plane march
+                                with the densities of four planes in LDS); bit for bit
                                 the same result */
     int32_t reserved;        /* must be 0 */
     double tau[2];           /* tau_A, tau_B > 1/2 (Eq. 2) */
@@ -76,10 +77,10 @@ size_t lb3_workspace_bytes(const lb3_config *cfg);
  * stream once. */
 int32_t lb3_init(const lb3_config *cfg, void *d_workspace, size_t bytes, void *hip_stream, lb3_handle **out);
 
-/* Advance by n >= 0 time steps (Eq. 2).  Fused: one kernel pass per step
- * (a plane march that keeps the densities of three planes in LDS).  Two
- * passes: densities of the pulled populations, then force, collision and
- * store. */
+/* Advance by n >= 0 time steps (Eq. 2).  Two passes (default): densities of
+ * the pulled populations, then force, collision and store.  Fused: one
+ * kernel pass per step (a plane march that keeps the densities of four
+ * planes in LDS and pulls the current plane a second time). */
 int32_t lb3_step(lb3_handle *h, int64_t n);
 
 /* rho_A, rho_B and the hydrodynamic velocity (u_x, u_y, u_z) of f(t) into
