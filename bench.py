@@ -157,13 +157,13 @@ BYTES_PER_LU_3D = {"f64": 38 * 8 + 16 + 38 * 8 + 16 + 38 * 8, "f32": 38 * 4 + 16
 BYTES_PER_LU_3D_FUSED = {"f64": 2 * 38 * 8, "f32": 2 * 38 * 4}
 
 
-def d3q19_line(lb, inputs, stream, storage="f64", steps=100, warmup=10, fused=False):
+def d3q19_line(lb, inputs, stream, storage="f64", steps=100, warmup=10, two_pass=False):
     from paper_2101_04847_amd import lb3
     w = inputs.D3_384
     rA, rB = inputs.rt3d_densities(w["nx"], w["ny"], w["nz"], w["seed"])
     lat = lb3.Lattice3(w["nx"], w["ny"], w["nz"], rA, rB, tau=(w["tau"], w["tau"]), G=w["G"],
                        g=((0.0, -w["g"], 0.0), (0.0, w["g"], 0.0)), storage=storage_code(lb, storage),
-                       stream=stream, fused=fused)
+                       stream=stream, two_pass=two_pass)
     del rA, rB
     ms, _ = time_steps(lat, steps, warmup, stream, chunk=steps)
     d = lat.diagnostics()
@@ -173,9 +173,9 @@ def d3q19_line(lb, inputs, stream, storage="f64", steps=100, warmup=10, fused=Fa
     torch.cuda.empty_cache()
     sites = w["nx"] * w["ny"] * w["nz"]
     mlups = sites / (ms / 1e3) / 1e6
-    bpl = BYTES_PER_LU_3D_FUSED[storage] if fused else BYTES_PER_LU_3D[storage]
+    bpl = BYTES_PER_LU_3D[storage] if two_pass else BYTES_PER_LU_3D_FUSED[storage]
     return {"workload": w["name"], "storage": storage, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4),
-            "kernels": ["lbk3::k3_fused"] if fused else ["lbk3::k3_density", "lbk3::k3_collide"],
+            "kernels": ["lbk3::k3_density", "lbk3::k3_collide"] if two_pass else ["lbk3::k3_fused"],
             "bytes_per_lu": bpl, "hbm_frac": round(bpl * sites / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "finite": d["finite"], "umax": d["umax"]}
 
@@ -210,7 +210,7 @@ def main() -> int:
     ap.add_argument("--report", default="", help="run the precision / ensemble studies, write JSON here")
     ap.add_argument("--d3q19-only", action="store_true",
                     help="time only the 3D (D3Q19) step on 384^3 in --storage (for kernel traces)")
-    ap.add_argument("--fused", action="store_true", help="with --d3q19-only: the fused 3D pass")
+    ap.add_argument("--two-pass", action="store_true", help="with --d3q19-only: the two-pass 3D step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the step shards across GPUs "
@@ -228,7 +228,7 @@ def main() -> int:
             print("the 3D step stores f64 or f32", file=sys.stderr)
             return 2
         print(json.dumps({"d3q19": d3q19_line(lb, inputs, stream, args.storage, steps=min(args.steps, 200),
-                                              warmup=min(args.warmup, 10), fused=args.fused)}), flush=True)
+                                              warmup=min(args.warmup, 10), two_pass=args.two_pass)}), flush=True)
         return 0
     if args.report:
         from paper_2101_04847_amd import studies
@@ -323,9 +323,9 @@ def main() -> int:
                                             wall_psi=lb.PSI_ZERO)
         # the D3Q19 extension on 384^3
         out["d3q19"] = []
-        for st, fu in (("f64", False), ("f32", False), ("f64", True)):
-            log("d3q19", st, "fused" if fu else "two passes")
-            out["d3q19"].append(d3q19_line(lb, inputs, stream, st, fused=fu))
+        for st, two in (("f64", False), ("f32", False), ("f64", True)):
+            log("d3q19", st, "two passes" if two else "fused")
+            out["d3q19"].append(d3q19_line(lb, inputs, stream, st, two_pass=two))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -41,10 +41,10 @@ typedef struct lb3_config {
     int32_t storage;         /* LB_F64 or LB_F32 (the arithmetic is FP64 in both) */
     int32_t diag_trim;       /* rows dropped next to each wall for the E_k average of
                                 lb3_diagnostics (>= 0, ny > 2 * diag_trim) */
-    int32_t fused;           /* 0 (default): two passes per step (densities, then
-                                force and collision); 1: one fused pass (a plane march
-                                with the densities of four planes in LDS); bit for bit
-                                the same result */
+    int32_t two_pass;        /* 0 (default): one fused pass per step (a plane march
+                                with the densities of four planes in LDS); 1: two
+                                passes (densities, then force and collision); bit for
+                                bit the same result */
     int32_t reserved;        /* must be 0 */
     double tau[2];           /* tau_A, tau_B > 1/2 (Eq. 2) */
     double G_AB;             /* Shan-Chen coupling of Eq. 5 */
@@ -77,10 +77,10 @@ size_t lb3_workspace_bytes(const lb3_config *cfg);
  * stream once. */
 int32_t lb3_init(const lb3_config *cfg, void *d_workspace, size_t bytes, void *hip_stream, lb3_handle **out);
 
-/* Advance by n >= 0 time steps (Eq. 2).  Two passes (default): densities of
- * the pulled populations, then force, collision and store.  Fused: one
- * kernel pass per step (a plane march that keeps the densities of four
- * planes in LDS and pulls the current plane a second time). */
+/* Advance by n >= 0 time steps (Eq. 2).  Fused (default): one kernel pass
+ * per step, a plane march that keeps the densities of four planes in LDS and
+ * the pulled populations in registers.  Two passes: densities of the pulled
+ * populations, then force, collision and store. */
 int32_t lb3_step(lb3_handle *h, int64_t n);
 
 /* rho_A, rho_B and the hydrodynamic velocity (u_x, u_y, u_z) of f(t) into

@@ -1,6 +1,6 @@
 // Host runtime of the 3D (D3Q19) entry points declared in include/lb3.h:
-// validation, workspace layout, initial state, the step (two passes, or one
-// fused pass), the field pass, reductions and state conversion.
+// validation, workspace layout, initial state, the step (one fused pass, or
+// two passes), the field pass, reductions and state conversion.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,7 +54,7 @@ int32_t validate3(const lb3_config *c)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(c->g[s][a])) return fail(LB_EINVAL, "g[%d][%d] is not finite", s, a);
     if (!c->rhoA0 || !c->rhoB0) return fail(LB_EINVAL, "initial densities are NULL");
-    if (c->fused != 0 && c->fused != 1) return fail(LB_EINVAL, "fused = %d must be 0 or 1", c->fused);
+    if (c->two_pass != 0 && c->two_pass != 1) return fail(LB_EINVAL, "two_pass = %d must be 0 or 1", c->two_pass);
     if (c->reserved != 0) return fail(LB_EINVAL, "reserved = %d must be 0", c->reserved);
     return LB_OK;
 }
@@ -231,7 +231,7 @@ int32_t lb3_step(lb3_handle *h, int64_t n)
 {
     if (!live3(h)) return fail(LB_ESTATE, "handle is not live");
     if (n < 0) return fail(LB_EINVAL, "n = %lld is negative", (long long)n);
-    if (!h->cfg.fused) {
+    if (h->cfg.two_pass) {
         const DensFn fd = pick_dens(h->cfg.storage, h->cfg.bc_y);
         const CollFn fc = pick_coll(h->cfg.storage, h->cfg.bc_y, false);
         const dim3 g = grid3(h);

@@ -5,10 +5,11 @@
 // segments of one lattice row adjacent, x fastest) holding post-collision
 // populations; f(t) is pulled: f_i(x) = f*_i(x - c_i), or f*_opp(i)(x) where
 // x - c_i lies beyond a y wall.  Two ways to run a step, both HBM-bound:
-//   k3_fused     one pass: a block owns a tile of the x-y plane and marches
-//                through a band of planes in z, keeping the densities of four
-//                planes in an LDS ring, so each population crosses HBM about
-//                once per read and once per write;
+//   k3_fused     one pass (the default): a block owns a tile of the x-y plane
+//                and marches through a band of planes in z, keeping the
+//                densities of four planes in an LDS ring and the pulled
+//                populations of two planes in registers, so each population
+//                crosses HBM about once per read and once per write;
 //   k3_density + k3_collide
 //                two passes with one thread per site: the densities go to a
 //                [z][y][2][pitch] FP64 buffer, then the populations are pulled
@@ -300,12 +301,12 @@ __global__ void __launch_bounds__(WX * WY) k3_collide(Lat3 L, int cur, Fields3 f
 // The fused step: one pass per time step.  A block of FX x FY threads owns
 // an (FX - 2) x (FY - 2) tile of the x-y plane plus a one-site halo and
 // marches through a band of planes in z.  Per plane every thread pulls its
-// site of the plane ahead and puts its densities into a ring of four density
-// planes in LDS; after one barrier the interior threads pull their site of
-// the current plane again (read one plane earlier, so from cache), take the
-// 18 neighbour densities from the ring and collide.  HBM then carries each
-// population about once per read and once per write.
-constexpr int FX = 64, FY = 12;
+// site of the plane ahead into registers and puts its densities into a ring
+// of four density planes in LDS; after one barrier the interior threads
+// collide the site they pulled one plane earlier (still in registers), with
+// the 18 neighbour densities from the ring.  Two register sets alternate
+// (the march is unrolled by two), so no population is read twice.
+constexpr int FX = 64, FY = 8;
 
 template <int ST, int BCY>
 __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
@@ -318,8 +319,8 @@ __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
     const int yu = blockIdx.y * (FY - 2) - 1 + ty;      // unwrapped row (wave-uniform)
     const int z0 = blockIdx.z * nzb;
     const int nplanes = min(nzb, L.nz - z0);
-    // the site whose densities this thread provides: x wraps; beyond a wall
-    // the wall row (mirror), or y wraps
+    // the site this thread pulls: x wraps; beyond a wall the wall row
+    // (mirror), or y wraps.  For interior threads it is (xu, yu) itself.
     int xs = xu % L.nx;
     if (xs < 0) xs += L.nx;
     int ys = yu;
@@ -331,34 +332,40 @@ __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
     }
     const bool interior = lane >= 1 && lane <= FX - 2 && ty >= 1 && ty <= FY - 2 && xu < L.nx && yu < L.ny;
     const void *src = L.f[cur];
-    auto densities = [&](int zp, int slot) {
+    // pull plane zp of this thread's site into f and its densities into a ring slot
+    auto pull_plane = [&](int zp, double (&f)[2][NQ3], int slot) {
         zp %= L.nz;
         if (zp < 0) zp += L.nz;
-        double f[2][NQ3];
         pull3<ST, BCY>(src, L, zp, ys, xs, f);
         ring[slot][0][ty][lane] = density3(f[0]);
         ring[slot][1][ty][lane] = density3(f[1]);
     };
+    double fa[2][NQ3], fb[2][NQ3];
     // ring slot of plane z0 + k is (k + 1) & 3
-    densities(z0 - 1, 0);
-    densities(z0, 1);
-    for (int k = 0; k < nplanes; ++k) {
+    pull_plane(z0 - 1, fb, 0);
+    pull_plane(z0, fa, 1);
+    // cf: plane z (pulled one plane earlier), nf: receives plane z + 1
+    auto plane = [&](int k, double (&cf)[2][NQ3], double (&nf)[2][NQ3]) {
         const int z = z0 + k;
-        densities(z + 1, (k + 2) & 3);
+        pull_plane(z + 1, nf, (k + 2) & 3);
         __syncthreads();
         if (interior) {
-            double f[2][NQ3];
-            pull3<ST, BCY>(src, L, z, yu, xu, f);
             double rho[2], S[2][3], a[2][3];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                rho[s] = density3(f[s]);
+                rho[s] = density3(cf[s]);
                 sc_sum3_nb([&](int i) { return ring[(k + 1 + c3z(i)) & 3][s][ty + c3y(i)][lane + c3x(i)]; }, S[s]);
             }
             accel3(L, S, a);
-            collide_store3<ST>(L, f, rho, a, cur, z, yu, xu);
+            collide_store3<ST>(L, cf, rho, a, cur, z, yu, xu);
         }
+    };
+    int k = 0;
+    for (; k + 2 <= nplanes; k += 2) {
+        plane(k, fa, fb);
+        plane(k + 1, fb, fa);
     }
+    if (k < nplanes) plane(k, fa, fb);
 }
 
 // Canonical f(t) [s][i][z][y][x] (or the rest equilibrium w_i rho_s of the

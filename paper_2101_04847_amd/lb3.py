@@ -19,7 +19,7 @@ NQ3 = 19
 class Lb3Config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_y", ctypes.c_int32), ("storage", ctypes.c_int32), ("diag_trim", ctypes.c_int32),
-                ("fused", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("two_pass", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("tau", ctypes.c_double * 2), ("G_AB", ctypes.c_double), ("g", (ctypes.c_double * 3) * 2),
                 ("rhoA0", _dp), ("rhoB0", _dp)]
 
@@ -54,7 +54,7 @@ EXPORTS3 = ("lb3_workspace_bytes", "lb3_init", "lb3_step", "lb3_fields", "lb3_di
 
 
 def make_config3(nx, ny, nz, rhoA0, rhoB0, *, tau=(1.0, 1.0), G=0.0, g=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
-                 bc_y=WALLS, storage=F64, diag_trim=0, fused=False):
+                 bc_y=WALLS, storage=F64, diag_trim=0, two_pass=False):
     """Build an Lb3Config; returns (config, keepalive list)."""
     a = np.ascontiguousarray(rhoA0, dtype=np.float64)
     b = np.ascontiguousarray(rhoB0, dtype=np.float64)
@@ -63,7 +63,7 @@ def make_config3(nx, ny, nz, rhoA0, rhoB0, *, tau=(1.0, 1.0), G=0.0, g=((0.0, 0.
     c = Lb3Config()
     c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
     c.bc_y, c.storage, c.diag_trim = int(bc_y), int(storage), int(diag_trim)
-    c.fused, c.reserved = (1 if fused else 0), 0
+    c.two_pass, c.reserved = (1 if two_pass else 0), 0
     c.tau[0], c.tau[1] = float(tau[0]), float(tau[1])
     c.G_AB = float(G)
     for s in range(2):
@@ -78,12 +78,12 @@ class Lattice3:
     """A 3D lattice on the GPU: x and z periodic, y walls or periodic."""
 
     def __init__(self, nx, ny, nz, rhoA0, rhoB0, *, tau=(1.0, 1.0), G=0.0, g=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)),
-                 bc_y=WALLS, storage=F64, diag_trim=0, fused=False, device="cuda", stream=None, poison=False):
+                 bc_y=WALLS, storage=F64, diag_trim=0, two_pass=False, device="cuda", stream=None, poison=False):
         import torch
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.device = torch.device(device)
         cfg, keep = make_config3(nx, ny, nz, rhoA0, rhoB0, tau=tau, G=G, g=g, bc_y=bc_y, storage=storage,
-                                 diag_trim=diag_trim, fused=fused)
+                                 diag_trim=diag_trim, two_pass=two_pass)
         nbytes = _lib.lb3_workspace_bytes(ctypes.byref(cfg))
         if nbytes == 0:
             raise LBError(LB_EINVAL, "lb3_workspace_bytes")

@@ -50,16 +50,16 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("fused", [False, True], ids=["two-pass", "fused"])
+@pytest.mark.parametrize("two_pass", [False, True], ids=["fused", "two-pass"])
 @pytest.mark.parametrize("nx,ny,nz,per,tau,G,g", CASES)
-def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g, fused):
+def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g, two_pass):
     _say("3d", nx, ny, nz, "periodic_y" if per else "walls", "tau", tau, "G", G, "g", g,
-         "fused" if fused else "two-pass")
+         "two-pass" if two_pass else "fused")
     R = min(5.0, 0.35 * min(nx, ny, nz))
     rA, rB = _drop(nx, ny, nz, R)
     gg = ((2e-5, -g, 1e-5), (0.0, g, 0.0))
     lat = lb3.Lattice3(nx, ny, nz, rA, rB, tau=tau, G=G, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS,
-                       poison=True, fused=fused)
+                       poison=True, two_pass=two_pass)
     p = orc3.Params3(nx=nx, ny=ny, nz=nz, tau=tau, G=G, g=gg, periodic_y=per)
     f = orc3.fill_equilibrium(p, rA, rB)
     assert _rel(lat.get_populations().cpu().numpy(), f) <= TOL
@@ -88,8 +88,8 @@ def test_3d_fused_equals_two_pass(lb3, per):
     rA, rB = _drop(nx, ny, nz, R=9.0)
     gg = ((0.0, -1e-4, 0.0), (0.0, 1e-4, 0.0))
     kw = dict(tau=(1.0, 0.9), G=1.3, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS)
-    a = lb3.Lattice3(nx, ny, nz, rA, rB, fused=True, **kw)
-    b = lb3.Lattice3(nx, ny, nz, rA, rB, fused=False, **kw)
+    a = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=False, **kw)
+    b = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=True, **kw)
     a.step(50)
     b.step(50)
     assert np.array_equal(a.get_populations().cpu().numpy(), b.get_populations().cpu().numpy())
