@@ -190,3 +190,25 @@ def test_3d_bench_size_two_steps(lb3):
         err = _rel(mg[k], mo[k])
         print(f"[case] {k} max rel err {err:.3e}", flush=True)
         assert err <= TOL, k
+
+
+def test_3d_non_finite_state_is_reported(lb3):
+    """A NaN planted in the populations (through set_populations) makes
+    lb3_diagnostics report LB_ENONFINITE: the binding raises, or returns
+    finite = False when asked not to check."""
+    import torch
+    from paper_2101_04847_amd.lb import LBError, LB_ENONFINITE
+    nx, ny, nz = 20, 10, 6
+    _say("3d non-finite detection")
+    rA, rB = _drop(nx, ny, nz, R=2.5)
+    lat = lb3.Lattice3(nx, ny, nz, rA, rB, tau=(1.0, 1.0), G=1.2)
+    assert lat.diagnostics()["finite"]
+    f = lat.get_populations()
+    f[0, 3, 2, 4, 7] = float("nan")
+    lat.set_populations(f)
+    with pytest.raises(LBError) as e:
+        lat.diagnostics()
+    assert e.value.code == LB_ENONFINITE
+    assert lat.diagnostics(check_finite=False)["finite"] is False
+    torch.cuda.synchronize()
+    lat.close()
