@@ -73,8 +73,10 @@ struct Fields3 {
 };
 
 // Pull the 38 populations of site (x, y, z) from the post-collision buffer.
-template <int ST, int BCY>
-__device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int y, int x, double (&f)[2][NQ3])
+// The values land in f as V: the storage type itself (kept in registers by
+// the fused pass) or double (converted on load; the conversion is exact).
+template <int ST, int BCY, class V>
+__device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int y, int x, V (&f)[2][NQ3])
 {
     using T = typename Tr<ST>::T;
     const int64_t row_bytes = L.rstride * (int64_t)sizeof(T);
@@ -103,36 +105,38 @@ __device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int
         const rsrc_t r = row_rsrc(src, zs * L.ny + ys, row_bytes);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
-            f[s][i] = (double)bload<T>(r, col, (unsigned)s * ss + (unsigned)seg * is);
+            f[s][i] = (V)bload<T>(r, col, (unsigned)s * ss + (unsigned)seg * is);
     }
 }
 
 // Eq. 1: rho_s = sum_i f_i in index order.
-__device__ __forceinline__ double density3(const double (&f)[NQ3])
+template <class V>
+__device__ __forceinline__ double density3(const V (&f)[NQ3])
 {
-    double r = f[0];
+    double r = (double)f[0];
 #pragma unroll
-    for (int i = 1; i < NQ3; ++i) r += f[i];
+    for (int i = 1; i < NQ3; ++i) r += (double)f[i];
     return r;
 }
 
 // j_s = sum_i f_i c_i in index order (terms with a zero component add nothing).
-__device__ __forceinline__ void momentum3(const double (&f)[NQ3], double &jx, double &jy, double &jz)
+template <class V>
+__device__ __forceinline__ void momentum3(const V (&f)[NQ3], double &jx, double &jy, double &jz)
 {
     double mx = 0.0, my = 0.0, mz = 0.0;
     bool fx = true, fy = true, fz = true;
 #pragma unroll
     for (int i = 1; i < NQ3; ++i) {
         if (c3x(i) != 0) {
-            mx = fx ? (c3x(i) > 0 ? f[i] : -f[i]) : (c3x(i) > 0 ? mx + f[i] : mx - f[i]);
+            mx = fx ? (c3x(i) > 0 ? (double)f[i] : -(double)f[i]) : (c3x(i) > 0 ? mx + (double)f[i] : mx - (double)f[i]);
             fx = false;
         }
         if (c3y(i) != 0) {
-            my = fy ? (c3y(i) > 0 ? f[i] : -f[i]) : (c3y(i) > 0 ? my + f[i] : my - f[i]);
+            my = fy ? (c3y(i) > 0 ? (double)f[i] : -(double)f[i]) : (c3y(i) > 0 ? my + (double)f[i] : my - (double)f[i]);
             fy = false;
         }
         if (c3z(i) != 0) {
-            mz = fz ? (c3z(i) > 0 ? f[i] : -f[i]) : (c3z(i) > 0 ? mz + f[i] : mz - f[i]);
+            mz = fz ? (c3z(i) > 0 ? (double)f[i] : -(double)f[i]) : (c3z(i) > 0 ? mz + (double)f[i] : mz - (double)f[i]);
             fz = false;
         }
     }
@@ -202,8 +206,8 @@ __device__ __forceinline__ void accel3(const Lat3 &L, const double (&S)[2][3], d
 
 // Collision of one site (Eq. 1-3 and the BGK relaxation of Eq. 2, velocity
 // shift) and the store of f*(t) at the site into buffer cur ^ 1.
-template <int ST>
-__device__ __forceinline__ void collide_store3(const Lat3 &L, const double (&f)[2][NQ3], const double (&rho)[2],
+template <int ST, class V>
+__device__ __forceinline__ void collide_store3(const Lat3 &L, const V (&f)[2][NQ3], const double (&rho)[2],
                                                const double (&a)[2][3], int cur, int z, int y, int x)
 {
     using T = typename Tr<ST>::T;
@@ -241,7 +245,8 @@ __device__ __forceinline__ void collide_store3(const Lat3 &L, const double (&f)[
             }
             if (c3z(i) != 0) cv = first ? (c3z(i) > 0 ? vz : -vz) : (c3z(i) > 0 ? cv + vz : cv - vz);
             const double feq = rho[s] * w3(i) * (1.0 + 3.0 * cv + 4.5 * cv * cv - 1.5 * vv);
-            const double post = f[s][i] - om * (f[s][i] - feq);   // Eq. 2
+            const double fi = (double)f[s][i];
+            const double post = fi - om * (fi - feq);   // Eq. 2
             bstore<LBK_NT_STORE ? lbk::CPOL_NT : 0>((T)post, wr, ox, (unsigned)(s * NQ3 + i) * is);
         }
     }
@@ -306,11 +311,16 @@ __global__ void __launch_bounds__(WX * WY) k3_collide(Lat3 L, int cur, Fields3 f
 // collide the site they pulled one plane earlier (still in registers), with
 // the 18 neighbour densities from the ring.  Two register sets alternate
 // (the march is unrolled by two), so no population is read twice.
+// The register sets hold the populations in the storage type (converted,
+// exactly, where they are used).  Two sets of FP64 populations plus the
+// collision need about 220 VGPRs, so a block of 512 threads (two waves per
+// SIMD) is the largest that fits; taller blocks spill and run slower.
 constexpr int FX = 64, FY = 8;
 
 template <int ST, int BCY>
 __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
 {
+    using V = typename Tr<ST>::T;
     __shared__ double ring[4][2][FY][FX];
     static_assert(FX == 64, "one wave per thread row: y is uniform across a wave");
     const int lane = threadIdx.x;
@@ -333,19 +343,19 @@ __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
     const bool interior = lane >= 1 && lane <= FX - 2 && ty >= 1 && ty <= FY - 2 && xu < L.nx && yu < L.ny;
     const void *src = L.f[cur];
     // pull plane zp of this thread's site into f and its densities into a ring slot
-    auto pull_plane = [&](int zp, double (&f)[2][NQ3], int slot) {
+    auto pull_plane = [&](int zp, V (&f)[2][NQ3], int slot) {
         zp %= L.nz;
         if (zp < 0) zp += L.nz;
         pull3<ST, BCY>(src, L, zp, ys, xs, f);
         ring[slot][0][ty][lane] = density3(f[0]);
         ring[slot][1][ty][lane] = density3(f[1]);
     };
-    double fa[2][NQ3], fb[2][NQ3];
+    V fa[2][NQ3], fb[2][NQ3];
     // ring slot of plane z0 + k is (k + 1) & 3
     pull_plane(z0 - 1, fb, 0);
     pull_plane(z0, fa, 1);
     // cf: plane z (pulled one plane earlier), nf: receives plane z + 1
-    auto plane = [&](int k, double (&cf)[2][NQ3], double (&nf)[2][NQ3]) {
+    auto plane = [&](int k, V (&cf)[2][NQ3], V (&nf)[2][NQ3]) {
         const int z = z0 + k;
         pull_plane(z + 1, nf, (k + 2) & 3);
         __syncthreads();

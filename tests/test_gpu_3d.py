@@ -79,15 +79,18 @@ def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g, two_pass):
     lat.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("per", [False, True], ids=["walls", "periodic_y"])
-def test_3d_fused_equals_two_pass(lb3, per):
-    """The fused pass and the two-pass step agree bit for bit, over three
-    z bands (the last one ragged), tiles ragged in x and y."""
+def test_3d_fused_equals_two_pass(lb3, per, storage):
+    """The fused pass and the two-pass step agree bit for bit (both storage
+    modes), over three z bands (the last one ragged), tiles ragged in x and
+    y."""
     nx, ny, nz = 130, 45, 70
-    _say("3d fused vs two-pass", nx, ny, nz, "periodic_y" if per else "walls")
+    _say("3d fused vs two-pass", nx, ny, nz, "periodic_y" if per else "walls", storage)
     rA, rB = _drop(nx, ny, nz, R=9.0)
     gg = ((0.0, -1e-4, 0.0), (0.0, 1e-4, 0.0))
-    kw = dict(tau=(1.0, 0.9), G=1.3, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS)
+    kw = dict(tau=(1.0, 0.9), G=1.3, g=gg, bc_y=lb3.PERIODIC_Y if per else lb3.WALLS,
+              storage=lb3.F64 if storage == "f64" else lb3.F32)
     a = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=False, **kw)
     b = lb3.Lattice3(nx, ny, nz, rA, rB, two_pass=True, **kw)
     a.step(50)
