@@ -214,7 +214,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the step shards across GPUs "
-              "as described in the design notes, but this build runs on a single MI355X.", file=sys.stderr)
+              "as described in the design notes, but this implementation runs on a single MI355X.", file=sys.stderr)
         return 2
 
     import torch
