@@ -59,61 +59,80 @@ static_assert(opp(1) == 3 && opp(2) == 4 && opp(3) == 1 && opp(4) == 2, "axis op
 static_assert(opp(5) == 7 && opp(6) == 8 && opp(7) == 5 && opp(8) == 6, "diagonal opposites");
 
 // ---------------------------------------------------------------------------
+// Sources of the pull of row y for column c (streaming with periodic x, and
+// either halfway bounce-back walls or periodic y): f_i(x) = f*_i(x - c_i), or
+// f*_opp(i)(x) where x - c_i lies beyond a wall.  Holds the buffer resources
+// of rows y, y - 1 and y + 1 (row y itself where that row lies beyond a
+// wall) and the per-lane byte offsets of the three source columns.
+template <int ST, int BCY>
+struct RowPull {
+    using T = typename Tr<ST>::T;
+    rsrc_t r0, rm, rp;
+    unsigned oc, om, op;    // source columns c, c - 1 (c_x = +1), c + 1 (c_x = -1)
+    unsigned is, ss;        // bytes between populations, between components
+    bool bb_lo, bb_hi;      // row y - 1 / y + 1 lies beyond a wall
+
+    __device__ __forceinline__ RowPull(const void *src, const Member &M, int y, int c)
+    {
+        const int nx = M.nx, ny = M.ny;
+        const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
+        is = (unsigned)M.istride * (unsigned)sizeof(T);
+        ss = (unsigned)M.sstride * (unsigned)sizeof(T);
+        oc = (unsigned)c * (unsigned)sizeof(T);
+        om = (unsigned)((c == 0) ? nx - 1 : c - 1) * (unsigned)sizeof(T);
+        op = (unsigned)((c == nx - 1) ? 0 : c + 1) * (unsigned)sizeof(T);
+        int ym = y - 1, yp = y + 1;   // source rows for c_y = +1 / -1
+        bb_lo = bb_hi = false;
+        if (BCY == BC_PERIODIC) {
+            if (ym < 0) ym = ny - 1;
+            if (yp >= ny) yp = 0;
+        } else {
+            bb_lo = ym < 0;
+            bb_hi = yp >= ny;
+            if (bb_lo) ym = y;   // bounce-back sources lie in row y
+            if (bb_hi) yp = y;
+        }
+        r0 = row_rsrc(src, y, row_bytes);
+        rm = row_rsrc(src, ym, row_bytes);
+        rp = row_rsrc(src, yp, row_bytes);
+    }
+
+    // The stored source of population i of component s; beyond a wall
+    // (bounce-back) the population comes from the same site with the
+    // reversed velocity.  i is a constant after unrolling.
+    __device__ __forceinline__ T load(int s, int i) const
+    {
+        const unsigned b = (unsigned)s * ss;
+        switch (i) {
+            case 0: return bload<T>(r0, oc, b + 0 * is);
+            case 1: return bload<T>(r0, om, b + 1 * is);
+            case 3: return bload<T>(r0, op, b + 3 * is);
+            case 2: return bload<T>(rm, oc, b + (bb_lo ? 4 : 2) * is);
+            case 5: return bload<T>(rm, bb_lo ? oc : om, b + (bb_lo ? 7 : 5) * is);
+            case 6: return bload<T>(rm, bb_lo ? oc : op, b + (bb_lo ? 8 : 6) * is);
+            case 4: return bload<T>(rp, oc, b + (bb_hi ? 2 : 4) * is);
+            case 7: return bload<T>(rp, bb_hi ? oc : op, b + (bb_hi ? 5 : 7) * is);
+            default: return bload<T>(rp, bb_hi ? oc : om, b + (bb_hi ? 6 : 8) * is);
+        }
+    }
+};
+
 // Pull the 18 pre-collision populations f(t) of column c, row y from the
-// post-collision buffer src (streaming with periodic x, and either halfway
-// bounce-back walls or periodic y).
+// post-collision buffer src, the loads grouped by source row.
 template <int ST, int BCY>
 __device__ __forceinline__ void pull_site(const void *src, const Member &M, int y, int c,
                                           typename Tr<ST>::C (&f)[2][NQ])
 {
     using Q = Tr<ST>;
-    using T = typename Q::T;
-    const int nx = M.nx, ny = M.ny;
-    const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
-    const unsigned is = (unsigned)M.istride * (unsigned)sizeof(T);   // bytes between populations
-    const unsigned ss = (unsigned)M.sstride * (unsigned)sizeof(T);   // bytes between components
-    // per-lane byte offsets of the three source columns
-    const unsigned oc = (unsigned)c * (unsigned)sizeof(T);
-    const unsigned om = (unsigned)((c == 0) ? nx - 1 : c - 1) * (unsigned)sizeof(T);  // c_x = +1
-    const unsigned op = (unsigned)((c == nx - 1) ? 0 : c + 1) * (unsigned)sizeof(T);  // c_x = -1
-    int ym = y - 1, yp = y + 1;                                   // source rows for c_y = +1 / -1
-    bool bb_lo = false, bb_hi = false;
-    if (BCY == BC_PERIODIC) {
-        if (ym < 0) ym = ny - 1;
-        if (yp >= ny) yp = 0;
-    } else {
-        bb_lo = ym < 0;
-        bb_hi = yp >= ny;
-        if (bb_lo) ym = y;   // bounce-back sources lie in row y
-        if (bb_hi) yp = y;
-    }
-    const rsrc_t r0 = row_rsrc(src, y, row_bytes);
-    const rsrc_t rm = row_rsrc(src, ym, row_bytes);
-    const rsrc_t rp = row_rsrc(src, yp, row_bytes);
+    const RowPull<ST, BCY> pr(src, M, y, c);
+    constexpr int ORDER[NQ] = {0, 1, 3, 2, 5, 6, 4, 7, 8};
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const unsigned b = (unsigned)s * ss;
-        // the nine sources; beyond a wall (bounce-back) the population comes
-        // from the same site with the reversed velocity, and rm / rp then
-        // address row y itself
-        const T v0 = bload<T>(r0, oc, b + 0 * is);
-        const T v1 = bload<T>(r0, om, b + 1 * is);
-        const T v3 = bload<T>(r0, op, b + 3 * is);
-        const T v2 = bload<T>(rm, oc, b + (bb_lo ? 4 : 2) * is);
-        const T v5 = bload<T>(rm, bb_lo ? oc : om, b + (bb_lo ? 7 : 5) * is);
-        const T v6 = bload<T>(rm, bb_lo ? oc : op, b + (bb_lo ? 8 : 6) * is);
-        const T v4 = bload<T>(rp, oc, b + (bb_hi ? 2 : 4) * is);
-        const T v7 = bload<T>(rp, bb_hi ? oc : op, b + (bb_hi ? 5 : 7) * is);
-        const T v8 = bload<T>(rp, bb_hi ? oc : om, b + (bb_hi ? 6 : 8) * is);
-        f[s][0] = Q::dec(v0, M.shift[s][0], M.iscale[s][0]);
-        f[s][1] = Q::dec(v1, M.shift[s][1], M.iscale[s][1]);
-        f[s][2] = Q::dec(v2, M.shift[s][2], M.iscale[s][2]);
-        f[s][3] = Q::dec(v3, M.shift[s][3], M.iscale[s][3]);
-        f[s][4] = Q::dec(v4, M.shift[s][4], M.iscale[s][4]);
-        f[s][5] = Q::dec(v5, M.shift[s][5], M.iscale[s][5]);
-        f[s][6] = Q::dec(v6, M.shift[s][6], M.iscale[s][6]);
-        f[s][7] = Q::dec(v7, M.shift[s][7], M.iscale[s][7]);
-        f[s][8] = Q::dec(v8, M.shift[s][8], M.iscale[s][8]);
+        typename Q::T v[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) v[ORDER[j]] = pr.load(s, ORDER[j]);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) f[s][i] = Q::dec(v[i], M.shift[s][i], M.iscale[s][i]);
     }
 }
 
@@ -756,7 +775,8 @@ __device__ __forceinline__ V shift_x(V v)
 //   q = a - 2 DIR, whose densities rho(t+1) of q - DIR, q, q + DIR = p are then
 //   known.
 // The populations of row a + 2 DIR are requested right after the step-1
-// collision, into the registers it has just consumed (two rotating sets).
+// collision of row a, into the registers it has just consumed (two rotating
+// sets); the last step-1 row requests none.
 // Only one pulled f(t+1) row is held in registers: row p's densities are
 // summed from its sources, and its populations are rebuilt (the same DPP
 // moves again) after the collision of row q.  This keeps the FP64 pass within
@@ -815,10 +835,15 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
     }
     if (inside(a0 + DIR)) pull_site<ST, BCY>(src, M, wrap(a0 + DIR), c, fb);
 
+    // march steps: step-1 rows a0 .. a0 + (K - 1) DIR
+    const int K = nrows + 4;
+
     // f1c: row a (then row a + 2 DIR); f1n: row a + DIR
     auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
         const int a = a0 + k * DIR;
         const bool in_a = inside(a), in_am = inside(a - DIR), in_ap = inside(a + DIR);
+        // row a + 2 DIR is needed unless this is the last step-1 row
+        const bool load_next = k + 1 < K && inside(a + 2 * DIR);
         // rho(t) of row a + DIR (its loads were issued one iteration ago)
         const double r1n[2] = {density(f1n[0]), density(f1n[1])};
         // --- step 1 at row a
@@ -850,7 +875,7 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 for (int j = 0; j < 3; ++j) out1[s][BW[j]] = P[s][opp(BW[j])];
         }
         // request row a + 2 DIR into the registers just freed
-        if (inside(a + 2 * DIR)) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
+        if (load_next) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
         // --- step 2: row p = a - DIR is pulled from the step-1 rows
         const int p = a - DIR;
         const bool pull_p = k >= 2 && inside(p);
@@ -921,7 +946,6 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
             r2c[s] = r2n[s];
         }
     };
-    const int K = nrows + 4;
     int k = 0;
     for (; k + 2 <= K; k += 2) {
         iter(k, fa, fb);
