@@ -43,18 +43,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str, storage: str, nx: int, ny: int):
+def measured_traffic(kernel: str, storage: str, nx: int, ny: int, tile=None):
     """HBM bytes per launch of the kernel from the committed counter summary,
-    if it was taken from the current kernel sources; else None."""
+    if it was taken from the current kernel sources and, when the record
+    names one, with the same tile; else None."""
     from paper_2101_04847_amd.profiling import kernel_source_hash
     path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_{nx}x{ny}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = json.load(fh)
-    if rec.get("source_hash") != kernel_source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+        recs = json.load(fh)
+    # one record, or a list of records taken at different tiles
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if rec.get("source_hash") != kernel_source_hash():
+            continue
+        if tile is not None and rec.get("tile") is not None and list(rec["tile"]) != list(tile):
+            continue
+        return rec.get("bytes_per_launch")
+    return None
 
 
 def storage_code(lb, name):
@@ -278,7 +284,7 @@ def main() -> int:
     launch_ms = ms_step * spp
     alg_bytes = BYTES_PER_LU[args.storage] * sites
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
-    traffic = measured_traffic(kernel, args.storage, wl.nx, wl.ny)
+    traffic = measured_traffic(kernel, args.storage, wl.nx, wl.ny, tile=[tx, th])
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": alg_bytes, "bytes_per_lu": BYTES_PER_LU[args.storage] // spp,

@@ -36,3 +36,25 @@ def test_hbm_fraction():
 
 def test_traffic_record_missing_is_null():
     assert bench.measured_traffic("step2", "f64", 123, 45) is None
+
+
+def test_traffic_record_needs_current_sources_and_tile(tmp_path, monkeypatch):
+    """A counter record counts only for the kernel sources it was taken
+    from and for the tile it names."""
+    import json
+    from paper_2101_04847_amd.profiling import kernel_source_hash
+    (tmp_path / "profiles").mkdir()
+    rec = {"source_hash": kernel_source_hash(), "bytes_per_launch": 123, "tile": [58, 8]}
+    path = tmp_path / "profiles" / "step2_f64_64x32_traffic.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 8]) == 123
+    assert bench.measured_traffic("step2", "f64", 64, 32) == 123
+    assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 10]) is None
+    other = dict(rec, tile=[58, 10], bytes_per_launch=456)
+    path.write_text(json.dumps([rec, other]))
+    assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 10]) == 456
+    assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 12]) is None
+    rec["source_hash"] = "0" * 16
+    path.write_text(json.dumps(rec))
+    assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 8]) is None
