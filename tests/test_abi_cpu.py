@@ -216,3 +216,48 @@ def test_lb3_workspace_and_bogus_handle(lb, lb3):
     d = lb3.Lb3Diag()
     assert lb3._lib.lb3_diagnostics(bogus, ctypes.byref(d)) == lb.LB_ESTATE
     assert lb3._lib.lb3_fields(bogus, None, None, None, None, None) == lb.LB_ESTATE
+
+
+# --- the C ABI from a plain C program (tests/c/lb_c_driver.c) ----------------
+
+def _c_driver():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("build_driver", os.path.join(ROOT, "tests", "c", "build_driver.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _write_driver_input(path, nx, ny, tau, G, g, rA, rB):
+    with open(path, "wb") as fh:
+        fh.write(np.array([nx, ny], dtype=np.int32).tobytes())
+        fh.write(np.array([tau[0], tau[1], G, g[0][0], g[0][1], g[1][0], g[1][1]], dtype=np.float64).tobytes())
+        fh.write(np.ascontiguousarray(rA, dtype=np.float64).tobytes())
+        fh.write(np.ascontiguousarray(rB, dtype=np.float64).tobytes())
+
+
+def test_c_driver_compiles_warning_free(lb, tmp_path):
+    """The C driver builds with gcc -Wall -Wextra -Werror against include/lb.h
+    and links liblb.so and the HIP runtime."""
+    d = _c_driver()
+    out = d.build(str(tmp_path / "drv"))
+    assert os.path.exists(out)
+
+
+def test_c_driver_reports_invalid_configuration(lb, tmp_path):
+    """From C, an invalid member (tau_A = 0.4 <= 1/2) makes lb_workspace_bytes
+    return 0 with a message from lb_last_error; no device call is made."""
+    import subprocess
+    d = _c_driver()
+    exe = d.build()
+    nx, ny = 16, 12
+    r = np.ones((ny, nx))
+    _write_driver_input(tmp_path / "in.bin", nx, ny, (0.4, 1.0), 1.0, ((0, 0), (0, 0)), r, r)
+    p = subprocess.run([exe, str(tmp_path / "in.bin"), str(tmp_path / "out.bin"), "3", "0", "0", "1"],
+                       capture_output=True, text=True, timeout=60)
+    assert p.returncode == 1, p.stderr
+    assert "tau" in p.stderr
+    rc = np.frombuffer(open(tmp_path / "out.bin", "rb").read(28), dtype=np.int32)
+    assert rc[0] == lb.LB_EINVAL
+    q = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert q.returncode == 2 and "usage" in q.stderr

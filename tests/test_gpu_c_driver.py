@@ -1,0 +1,81 @@
+"""GPU parity of liblb driven from a plain C program (tests/c/lb_c_driver.c):
+the C ABI of include/lb.h used with the HIP runtime alone, no Python binding
+and no PyTorch in the process that computes.  The program's populations,
+fields and diagnostics must match the FP64 oracle as the binding's do
+(1e-12 relative).
+
+The program is built by __graft_entry__.build() (or tests/c/build_driver.py);
+each case runs it as a child process under a time limit.
+"""
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_04847_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EXE = os.path.join(ROOT, "tests", "c", "lb_c_driver")
+TOL = 1e-12
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+CASES = [
+    # nx, ny, steps, forcing, bc_y, steps_per_pass, tau, G, g
+    (70, 33, 61, 0, 0, 2, (1.0, 1.0), 1.5, 1e-4),     # two-step passes and a final single step
+    (70, 33, 20, 1, 1, 1, (0.9, 0.9), 1.2, 1e-4),     # Guo forcing (equal taus), periodic y, single steps
+    (130, 21, 40, 0, 0, 0, (0.53, 0.53), 0.1381, 9e-6),   # the paper's immiscible tau and G, timed pass
+]
+
+
+@pytest.mark.parametrize("nx,ny,steps,forcing,bc,spp,tau,G,g", CASES)
+def test_c_program_matches_oracle(tmp_path, nx, ny, steps, forcing, bc, spp, tau, G, g):
+    print("[case] C driver", nx, ny, steps, "guo" if forcing else "shift", "periodic_y" if bc else "walls",
+          "spp", spp, flush=True)
+    assert os.path.exists(EXE), "tests/c/lb_c_driver is not built (run __graft_entry__.build())"
+    rA, rB = inputs.multi_mode(nx, ny, 7)
+    gg = ((0.0, -g), (0.0, g))
+    with open(tmp_path / "in.bin", "wb") as fh:
+        fh.write(np.array([nx, ny], dtype=np.int32).tobytes())
+        fh.write(np.array([tau[0], tau[1], G, gg[0][0], gg[0][1], gg[1][0], gg[1][1]]).tobytes())
+        fh.write(np.ascontiguousarray(rA, dtype=np.float64).tobytes())
+        fh.write(np.ascontiguousarray(rB, dtype=np.float64).tobytes())
+    p = subprocess.run([EXE, str(tmp_path / "in.bin"), str(tmp_path / "out.bin"), str(steps), str(forcing),
+                        str(bc), str(spp)], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stderr
+    raw = open(tmp_path / "out.bin", "rb").read()
+    n = nx * ny
+    rc = np.frombuffer(raw, dtype=np.int32, count=7, offset=0)
+    assert (rc == 0).all(), rc
+    t = int(np.frombuffer(raw, dtype=np.int64, count=1, offset=28)[0])
+    dv = np.frombuffer(raw, dtype=np.float64, count=7, offset=36)
+    finite = int(np.frombuffer(raw, dtype=np.int32, count=1, offset=92)[0])
+    f_gpu = np.frombuffer(raw, dtype=np.float64, count=18 * n, offset=96).reshape(2, 9, ny, nx)
+    fld = np.frombuffer(raw, dtype=np.float64, count=4 * n, offset=96 + 144 * n).reshape(4, ny, nx)
+    assert len(raw) == 96 + 144 * n + 32 * n
+    assert t == steps and finite == 1
+
+    po = oracle.Params(nx=nx, ny=ny, tau=tau, G=G, g=gg, forcing=forcing, periodic_y=bool(bc))
+    f = oracle.run(po, oracle.fill_equilibrium(po, rA, rB), steps)
+    assert _rel(f_gpu, f) <= TOL
+    m = oracle.macro(po, f)
+    for k, a in zip(("rhoA", "rhoB", "ux", "uy"), fld):
+        assert _rel(a, m[k]) <= TOL, k
+    # averages against the oracle's sums, within 1e-12 of the sum of |terms|
+    d = oracle.diagnostics(po, f, trim=1)
+    D = slice(1, ny - 1)
+    rho = m["rhoA"] + m["rhoB"]
+    yj = (np.arange(ny) - 0.5 * (ny - 1))[:, None]
+    fy = m["rhoA"] * gg[0][1] + m["rhoB"] * gg[1][1]
+    scale = {"mass_A": np.sum(np.abs(m["rhoA"])), "mass_B": np.sum(np.abs(m["rhoB"])),
+             "Ek": np.mean((0.5 * rho * (m["ux"] ** 2 + m["uy"] ** 2))[D]), "Ep": np.mean(np.abs(yj * fy)[D]),
+             "buoyancy": np.mean(np.abs(m["uy"] * fy)[D]), "omega2": d["omega2"], "umax": d["umax"]}
+    for k, v in zip(("mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "umax"), dv):
+        assert abs(v - d[k]) <= 1e-12 * scale[k], (k, v, d[k])
