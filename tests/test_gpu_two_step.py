@@ -133,6 +133,27 @@ def test_two_step_equals_single_step(lb, storage, forcing):
     two.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16s"])
+@pytest.mark.parametrize("bc", [0, 1], ids=["walls", "periodic_y"])
+def test_two_step_ragged_bands_reduced_precision(lb, storage, bc):
+    """The 32-bit-arithmetic fused pass (three rotating register sets) equals
+    single steps bit for bit for band heights whose march lengths leave every
+    remainder modulo three, with a ragged last band and a ragged last tile."""
+    st = {"f32": lb.F32, "bf16s": lb.BF16S}[storage]
+    for band in (1, 2, 3, 5, 7):
+        _say("two-step ragged bands", storage, "periodic_y" if bc else "walls", "band", band)
+        m = _member(lb, 130, 23, seed=5, g=1e-4)
+        one = _lattice(lb, [m], spp=1, chunk=-1, bc=bc, storage=st, tile=(64, 16))
+        two = _lattice(lb, [m], spp=2, band=band, chunk=-1, bc=bc, storage=st)
+        for n in (2, 5):
+            one.step(n)
+            two.step(n)
+            assert np.array_equal(one.get_populations(0).cpu().numpy(), two.get_populations(0).cpu().numpy()), \
+                (band, n)
+        one.close()
+        two.close()
+
+
 @pytest.mark.parametrize("chunk", [2, 6, 8])
 def test_two_step_graph_parity(lb, chunk):
     """Graphs of an odd number of passes flip the buffer parity on every
