@@ -83,7 +83,7 @@ def test_3d_matches_oracle(lb3, nx, ny, nz, per, tau, G, g, two_pass):
 @pytest.mark.parametrize("per", [False, True], ids=["walls", "periodic_y"])
 def test_3d_fused_equals_two_pass(lb3, per, storage):
     """The fused pass and the two-pass step agree bit for bit (both storage
-    modes), over three z bands (the last one ragged), tiles ragged in x and
+    modes), over nine z bands (the last one ragged), tiles ragged in x and
     y."""
     nx, ny, nz = 130, 45, 70
     _say("3d fused vs two-pass", nx, ny, nz, "periodic_y" if per else "walls", storage)
