@@ -549,7 +549,7 @@ int32_t choose_tiles(lb_handle *h)
         std::vector<int> th2(nm, c.tile_h > 0 ? c.tile_h : 12);
         float best2 = 0.0f;
         if (c.tile_h == 0 || spp == 0) {
-            std::vector<int> heights = {6, 8, 10, 12, 16, 24};
+            std::vector<int> heights = {6, 7, 8, 9, 10, 12, 16, 24};
             if (c.tile_h > 0) heights = {c.tile_h};
             int32_t rc = search(heights, 12, [&](const std::vector<int> &thm, float &t) {
                 return time_shape2(h, thm, reps, t);
