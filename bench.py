@@ -131,11 +131,22 @@ def cpu_baseline(wl, target_s: float = 40.0) -> dict:
     t0 = time.perf_counter()
     oracle.run_inplace(p, f, n)
     dt = time.perf_counter() - t0
+    # the same step on one thread (one step of the full lattice)
+    cores = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run_inplace(p, f, 1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
     del f
-    return {"value": round(wl.nx * wl.ny * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+    return {"value": round(wl.nx * wl.ny * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} steps of the full {wl.nx}x{wl.ny} lattice after 2 untimed steps "
-                      f"(FP64, OpenMP over rows, {dt:.1f} s)"}
+                      f"(FP64, OpenMP over rows, {dt:.1f} s)",
+            "single_thread": {"value": round(wl.nx * wl.ny / dt1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"1 further step of the same lattice on one thread ({dt1:.1f} s)"}}
 
 
 def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0, **walls):

@@ -58,3 +58,15 @@ def test_traffic_record_needs_current_sources_and_tile(tmp_path, monkeypatch):
     rec["source_hash"] = "0" * 16
     path.write_text(json.dumps(rec))
     assert bench.measured_traffic("step2", "f64", 64, 32, tile=[58, 8]) is None
+
+
+def test_cpu_baseline_reports_all_cores_and_one_thread():
+    """The oracle leg of bench.py on a small lattice: the rate on every host
+    thread and on one thread, and the thread count restored afterwards."""
+    import oracle
+    from paper_2101_04847_amd import inputs
+    before = oracle.threads()
+    r = bench.cpu_baseline(inputs.Workload(96, 40, seed=3, name="tiny"), target_s=0.05)
+    assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["value"] > 0
+    assert r["cores"] == before == oracle.threads()
+    assert r["single_thread"]["value"] > 0 and r["single_thread"]["unit"] == "MLUPS"
