@@ -3,6 +3,7 @@
     python -m paper_2101_04847_amd.profiling trace <kernel_trace.csv> <kernel-regex> <n_last> [out.md]
     python -m paper_2101_04847_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <kernel-regex> <copy-bytes> <storage> <nx> <ny> [out.json]
+    python -m paper_2101_04847_amd.profiling sq <counter_collection.csv> <kernel-regex> <n_simd> <n_xcd>
     python -m paper_2101_04847_amd.profiling copy <bytes>
 
 `copy` runs a plain device-to-device copy of the given size ten times (the
@@ -16,6 +17,17 @@ same kernel belong to tile tuning and warm-up).
 HBM bytes per launch, each counter scaled by the factor that makes it read
 the known size of a plain copy kernel, and records the hash of the kernel
 sources so that a stale record is ignored by bench.py.
+
+`sq` turns one run of the shader-sequencer counters SQ_WAVE_CYCLES,
+SQ_WAIT_INST_ANY, SQ_WAIT_ANY, SQ_ACTIVE_INST_ANY, SQ_ACTIVE_INST_VALU,
+SQ_ACTIVE_INST_VMEM, SQ_INSTS_VALU and GRBM_GUI_ACTIVE (means per dispatch of
+the matching kernel) into shares of the waves' lifetime (waiting on a memory
+or other dependency, issuing any instruction, a VALU or a vector-memory
+instruction) and the VALU busy fraction of the chip, SQ_ACTIVE_INST_VALU x 4
+/ n_simd / (GRBM_GUI_ACTIVE / n_xcd): the usual rocprof definition, with
+GRBM_GUI_ACTIVE summed over the n_xcd dies (n_simd = 4 per CU).  A second
+estimate counts 4 cycles per wave-64 VALU instruction: SQ_INSTS_VALU x 4 /
+n_simd / (GRBM_GUI_ACTIVE / n_xcd).
 """
 from __future__ import annotations
 
@@ -82,6 +94,23 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, regex, copy_by
             "copy_bytes": copy_bytes}
 
 
+SQ_COUNTERS = ("SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VALU",
+               "SQ_ACTIVE_INST_VMEM", "SQ_INSTS_VALU", "GRBM_GUI_ACTIVE")
+
+
+def sq_summary(path: str, regex: str, n_simd: int, n_xcd: int = 1) -> dict:
+    m = {c: _counter_mean(path, regex, c)[0] for c in SQ_COUNTERS}
+    w = m["SQ_WAVE_CYCLES"]
+    cycles = m["GRBM_GUI_ACTIVE"] / n_xcd   # cycles of the kernel on one die
+    return {"dispatches": _counter_mean(path, regex, "SQ_WAVE_CYCLES")[1],
+            "wait_dependency": m["SQ_WAIT_INST_ANY"] / w, "wait_any": m["SQ_WAIT_ANY"] / w,
+            "issue_any": m["SQ_ACTIVE_INST_ANY"] / w, "issue_valu": m["SQ_ACTIVE_INST_VALU"] / w,
+            "issue_vmem": m["SQ_ACTIVE_INST_VMEM"] / w,
+            "valu_busy": m["SQ_ACTIVE_INST_VALU"] * 4.0 / n_simd / cycles,
+            "valu_busy_from_insts": m["SQ_INSTS_VALU"] * 4.0 / n_simd / cycles,
+            "valu_insts": m["SQ_INSTS_VALU"], "cycles": cycles}
+
+
 def copy_kernel(nbytes: float) -> None:
     import torch
     n = int(nbytes)
@@ -100,6 +129,10 @@ def main(argv):
     if argv[0] == "trace":
         s = trace_summary(argv[1], argv[2], int(argv[3]))
         text = json.dumps(s, indent=1)
+    elif argv[0] == "sq":
+        s = sq_summary(argv[1], argv[2], int(argv[3]), int(argv[4]))
+        text = json.dumps(s, indent=1)
+        argv = argv[:5]
     elif argv[0] == "traffic":
         s = traffic(argv[1], argv[2], argv[3], argv[4], argv[5], float(argv[6]), argv[7], int(argv[8]), int(argv[9]))
         text = json.dumps(s, indent=1)

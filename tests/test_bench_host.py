@@ -70,3 +70,25 @@ def test_cpu_baseline_reports_all_cores_and_one_thread():
     assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["value"] > 0
     assert r["cores"] == before == oracle.threads()
     assert r["single_thread"]["value"] > 0 and r["single_thread"]["unit"] == "MLUPS"
+
+
+def test_sq_summary_arithmetic(tmp_path):
+    """The shader-sequencer summary: shares of wave cycles and the VALU busy
+    fraction SQ_ACTIVE_INST_VALU x 4 / n_simd / GRBM_GUI_ACTIVE, as means over
+    the dispatches of the matching kernel only."""
+    from paper_2101_04847_amd import profiling
+    vals = {"SQ_WAVE_CYCLES": 1000.0, "SQ_WAIT_INST_ANY": 400.0, "SQ_WAIT_ANY": 500.0, "SQ_ACTIVE_INST_ANY": 300.0,
+            "SQ_ACTIVE_INST_VALU": 2560.0, "SQ_ACTIVE_INST_VMEM": 50.0, "SQ_INSTS_VALU": 7.0, "GRBM_GUI_ACTIVE": 20.0}
+    lines = ["Kernel_Name,Counter_Name,Counter_Value"]
+    for k, v in vals.items():
+        lines.append(f'"void lbk::k_step2<0, 0, 0>(x)",{k},{v}')
+        lines.append(f'"void lbk::k_step2<0, 0, 0>(x)",{k},{v * 3}')
+        lines.append(f'"other",{k},1')
+    path = tmp_path / "c.csv"
+    path.write_text("\n".join(lines) + "\n")
+    s = profiling.sq_summary(str(path), r"k_step2<0, 0, 0>", 1024, 8)
+    assert s["dispatches"] == 2
+    assert s["wait_dependency"] == pytest.approx(0.4) and s["issue_any"] == pytest.approx(0.3)
+    assert s["cycles"] == pytest.approx(20.0 * 2 / 8)
+    assert s["valu_busy"] == pytest.approx(2560.0 * 2 * 4 / 1024 / (20.0 * 2 / 8))
+    assert s["valu_busy_from_insts"] == pytest.approx(7.0 * 2 * 4 / 1024 / (20.0 * 2 / 8))
