@@ -237,11 +237,11 @@ def _write_driver_input(path, nx, ny, tau, G, g, rA, rB):
 
 
 def test_c_driver_compiles_warning_free(lb, tmp_path):
-    """The C driver builds with gcc -Wall -Wextra -Werror against include/lb.h
-    and links liblb.so and the HIP runtime."""
+    """The C drivers build with gcc -Wall -Wextra -Werror against include/lb.h
+    and include/lb3.h and link liblb.so and the HIP runtime."""
     d = _c_driver()
-    out = d.build(str(tmp_path / "drv"))
-    assert os.path.exists(out)
+    assert os.path.exists(d.build(str(tmp_path / "drv")))
+    assert os.path.exists(d.build(str(tmp_path / "drv3"), d.SRC3))
 
 
 def test_c_driver_reports_invalid_configuration(lb, tmp_path):
@@ -261,3 +261,24 @@ def test_c_driver_reports_invalid_configuration(lb, tmp_path):
     assert rc[0] == lb.LB_EINVAL
     q = subprocess.run([exe], capture_output=True, text=True, timeout=60)
     assert q.returncode == 2 and "usage" in q.stderr
+
+
+
+def test_c_driver_3d_reports_invalid_configuration(lb, tmp_path):
+    """From C, lb3_workspace_bytes rejects tau_B = 0.5 with a message."""
+    import subprocess
+    d = _c_driver()
+    exe = d.build(d.EXE3, d.SRC3)
+    nx, ny, nz = 8, 6, 5
+    r = np.ones((nz, ny, nx))
+    with open(tmp_path / "in.bin", "wb") as fh:
+        fh.write(np.array([nx, ny, nz], dtype=np.int32).tobytes())
+        fh.write(np.array([1.0, 0.5, 1.0, 0, 0, 0, 0, 0, 0], dtype=np.float64).tobytes())
+        fh.write(r.tobytes())
+        fh.write(r.tobytes())
+    p = subprocess.run([exe, str(tmp_path / "in.bin"), str(tmp_path / "out.bin"), "3", "0", "0", "0"],
+                       capture_output=True, text=True, timeout=60)
+    assert p.returncode == 1, p.stderr
+    assert "tau" in p.stderr
+    rc = np.frombuffer(open(tmp_path / "out.bin", "rb").read(28), dtype=np.int32)
+    assert rc[0] == lb.LB_EINVAL

@@ -21,11 +21,20 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EXE = os.path.join(ROOT, "tests", "c", "lb_c_driver")
+EXE3 = os.path.join(ROOT, "tests", "c", "lb3_c_driver")
 TOL = 1e-12
 
 
 def _rel(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(np.asarray(b))), 1e-300))
+
+
+def _ensure_built(exe):
+    if not os.path.exists(exe):
+        # normally built by __graft_entry__.build(); gcc takes well under a second
+        import runpy
+        runpy.run_path(os.path.join(ROOT, "tests", "c", "build_driver.py"))["build_all"]()
+    assert os.path.exists(exe), exe + " could not be built"
 
 
 CASES = [
@@ -40,11 +49,7 @@ CASES = [
 def test_c_program_matches_oracle(tmp_path, nx, ny, steps, forcing, bc, spp, tau, G, g):
     print("[case] C driver", nx, ny, steps, "guo" if forcing else "shift", "periodic_y" if bc else "walls",
           "spp", spp, flush=True)
-    if not os.path.exists(EXE):
-        # normally built by __graft_entry__.build(); gcc takes well under a second
-        import runpy
-        runpy.run_path(os.path.join(ROOT, "tests", "c", "build_driver.py"))["build"]()
-    assert os.path.exists(EXE), "tests/c/lb_c_driver could not be built"
+    _ensure_built(EXE)
     rA, rB = inputs.multi_mode(nx, ny, 7)
     gg = ((0.0, -g), (0.0, g))
     with open(tmp_path / "in.bin", "wb") as fh:
@@ -84,3 +89,54 @@ def test_c_program_matches_oracle(tmp_path, nx, ny, steps, forcing, bc, spp, tau
              "buoyancy": np.mean(np.abs(m["uy"] * fy)[D]), "omega2": d["omega2"], "umax": d["umax"]}
     for k, v in zip(("mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "umax"), dv):
         assert abs(v - d[k]) <= 1e-12 * scale[k], (k, v, d[k])
+
+
+CASES3 = [
+    # nx, ny, nz, steps, bc_y, storage, two_pass
+    (70, 13, 9, 21, 0, 0, 0),     # fused pass, walls, FP64: two z bands, the second ragged
+    (64, 11, 7, 12, 1, 0, 1),     # two passes, periodic y
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,steps,bc,storage,two_pass", CASES3)
+def test_c_program_3d_matches_oracle(tmp_path, nx, ny, nz, steps, bc, storage, two_pass):
+    from oracle import lb3 as orc3
+    print("[case] C driver 3D", nx, ny, nz, steps, "periodic_y" if bc else "walls",
+          "two-pass" if two_pass else "fused", flush=True)
+    _ensure_built(EXE3)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d = np.sqrt((x - nx / 2 + 0.3) ** 2 + (y - ny / 3 + 0.2) ** 2 + (z - nz / 2 - 0.4) ** 2) - 3.0
+    sh = 0.5 * (1 - np.tanh(d / 1.5))
+    rA, rB = 0.06 + sh, 0.06 + 0.95 * (1 - sh)
+    tau, G = (1.0, 0.9), 1.3
+    gg = ((1e-5, -1e-4, 0.0), (0.0, 1e-4, 2e-5))
+    with open(tmp_path / "in.bin", "wb") as fh:
+        fh.write(np.array([nx, ny, nz], dtype=np.int32).tobytes())
+        fh.write(np.array([tau[0], tau[1], G, *gg[0], *gg[1]]).tobytes())
+        fh.write(np.ascontiguousarray(rA, dtype=np.float64).tobytes())
+        fh.write(np.ascontiguousarray(rB, dtype=np.float64).tobytes())
+    p = subprocess.run([EXE3, str(tmp_path / "in.bin"), str(tmp_path / "out.bin"), str(steps), str(bc),
+                        str(storage), str(two_pass)], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stderr
+    raw = open(tmp_path / "out.bin", "rb").read()
+    n = nx * ny * nz
+    rc = np.frombuffer(raw, dtype=np.int32, count=7, offset=0)
+    assert (rc == 0).all(), rc
+    t = int(np.frombuffer(raw, dtype=np.int64, count=1, offset=28)[0])
+    dv = np.frombuffer(raw, dtype=np.float64, count=4, offset=36)
+    finite = int(np.frombuffer(raw, dtype=np.int32, count=1, offset=68)[0])
+    f_gpu = np.frombuffer(raw, dtype=np.float64, count=38 * n, offset=72).reshape(2, 19, nz, ny, nx)
+    fld = np.frombuffer(raw, dtype=np.float64, count=5 * n, offset=72 + 304 * n).reshape(5, nz, ny, nx)
+    assert len(raw) == 72 + 304 * n + 40 * n
+    assert t == steps and finite == 1
+
+    po = orc3.Params3(nx=nx, ny=ny, nz=nz, tau=tau, G=G, g=gg, periodic_y=bool(bc))
+    f = orc3.run(po, orc3.fill_equilibrium(po, rA, rB), steps)
+    assert _rel(f_gpu, f) <= TOL
+    m = orc3.macro(po, f)
+    for k, a in zip(("rhoA", "rhoB", "ux", "uy", "uz"), fld):
+        assert _rel(a, m[k]) <= TOL, k
+    u2 = m["ux"] ** 2 + m["uy"] ** 2 + m["uz"] ** 2
+    ek = np.mean(0.5 * (m["rhoA"] + m["rhoB"]) * u2)
+    for v, want in zip(dv, (m["rhoA"].sum(), m["rhoB"].sum(), ek, np.sqrt(u2.max()))):
+        assert abs(v - want) <= 1e-12 * abs(want), (v, want)
