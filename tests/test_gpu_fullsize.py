@@ -4,7 +4,8 @@ times (pass and tile shape chosen by timing, 100-step graphs replaced here by
 that both the fused two-step pass and the single step run): 10000 x 5000,
 FP64, velocity shift forcing, 32 random interface modes.  The oracle advances
 the same initial densities by three steps; every density and velocity of the
-lattice is compared."""
+lattice is compared, and the densities of the FP32 and BF16S lattices (each in
+the configuration the benchmark times) within their formats' bounds."""
 import numpy as np
 import pytest
 
@@ -32,6 +33,17 @@ def test_production_size_three_steps():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    # the reduced-precision benchmark lines in their own timed configurations
+    # (FP32: the fused pass; BF16S: the single step), densities only
+    reduced = {}
+    for name, st in (("f32", lb.F32), ("bf16s", lb.BF16S)):
+        lr = lb.Lattice([m], storage=st, graph_chunk=2)
+        print("[case] full size", name, "steps per pass", lr.steps_per_pass, "tile shape", lr.tile_shape(), flush=True)
+        lr.step(3)
+        reduced[name] = {k: v.cpu().numpy() for k, v in lr.fields(0).items() if k in ("rhoA", "rhoB")}
+        lr.close()
+        del lr
+        torch.cuda.empty_cache()
 
     p = oracle.Params(nx=wl.nx, ny=wl.ny, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
     f = oracle.fill_equilibrium(p, rA, rB)
@@ -43,6 +55,12 @@ def test_production_size_three_steps():
         err = np.max(np.abs(fg[k] - mo[k])) / np.max(np.abs(mo[k]))
         print(f"[case] {k} max rel err {err:.3e}", flush=True)
         assert err <= 1e-12, k
+    # bounds of the one-step reduced-precision test, times the three steps
+    for name, tol in (("f32", 1.5e-6), ("bf16s", 6e-2)):
+        for k in ("rhoA", "rhoB"):
+            err = np.max(np.abs(reduced[name][k] - mo[k])) / np.max(np.abs(mo[k]))
+            print(f"[case] {name} {k} max rel err {err:.3e}", flush=True)
+            assert err <= tol, (name, k, err)
     from oracle import interface
     io = interface.interface_length(mo["rhoA"], mo["rhoB"], 10)
     for k in ("n0", "n90", "n45", "n135", "length"):
