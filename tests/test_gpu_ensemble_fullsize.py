@@ -1,0 +1,54 @@
+"""Parity of the 16-member FP32 ensemble in the launch configuration the
+benchmark times (4 x 1024 x 512 + 8 x 2048 x 1024 + 4 x 4096 x 2048, G
+alternating 0.5 / 1.5, one launch per pass over all members, pass and band
+heights chosen by timing per size class, 2-step graphs): after three steps
+every member's densities are within the FP32 bound of the FP64 oracle run of
+that member alone, and the mass of each component is conserved."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_04847_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(600)
+def test_ensemble_16_fp32_three_steps():
+    import torch
+    from paper_2101_04847_amd import lb
+    assert torch.cuda.is_available()
+    wls = inputs.ensemble_16()
+    print("[case] ensemble of", len(wls), "FP32", flush=True)
+    members = []
+    dens = []
+    for wl in wls:
+        rA, rB = wl.densities()
+        dens.append((rA, rB))
+        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity))
+    lat = lb.Lattice(members, storage=lb.F32, graph_chunk=2)
+    print("[case] steps per pass", lat.steps_per_pass, "tiles", sorted({lat.tile_shape(k) for k in range(len(wls))}),
+          flush=True)
+    m0 = [lat.diagnostics(k) for k in range(len(wls))]
+    lat.step(3)
+    got = []
+    for k in range(len(wls)):
+        f = lat.fields(k)
+        got.append({q: f[q].cpu().numpy() for q in ("rhoA", "rhoB")})
+        d = lat.diagnostics(k)
+        for s in ("mass_A", "mass_B"):
+            assert abs(d[s] - m0[k][s]) <= 1e-6 * m0[k][s], (k, s)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    worst = 0.0
+    for k, wl in enumerate(wls):
+        p = oracle.Params(nx=wl.nx, ny=wl.ny, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
+        f = oracle.fill_equilibrium(p, *dens[k])
+        oracle.run_inplace(p, f, 3)
+        mo = oracle.macro(p, f)
+        for q in ("rhoA", "rhoB"):
+            err = np.max(np.abs(got[k][q] - mo[q])) / np.max(np.abs(mo[q]))
+            worst = max(worst, err)
+            assert err <= 1.5e-6, (k, wl.nx, wl.ny, wl.G, q, err)
+    print(f"[case] worst density rel err over the members {worst:.3e}", flush=True)
