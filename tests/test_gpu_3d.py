@@ -170,7 +170,7 @@ def test_3d_medium_lattice(lb3):
 def test_3d_bench_size_two_steps(lb3):
     """The benchmark's 3D lattice (384^3, 8 random interface modes, walls,
     tau = 1, G = 1.5, g = 1e-5): two steps, every density and velocity
-    against the oracle."""
+    against the oracle; the FP32 lattice's densities within 1e-6."""
     import torch
     from paper_2101_04847_amd import inputs
     w = inputs.D3_384
@@ -184,6 +184,13 @@ def test_3d_bench_size_two_steps(lb3):
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    # the FP32 lattice of the benchmark's FP32 line: densities within the format's bound
+    l32 = lb3.Lattice3(nx, ny, nz, rA, rB, tau=(w["tau"], w["tau"]), G=w["G"], g=gg, storage=lb3.F32)
+    l32.step(2)
+    m32 = {k: v.cpu().numpy() for k, v in l32.fields().items() if k in ("rhoA", "rhoB")}
+    l32.close()
+    del l32
+    torch.cuda.empty_cache()
     p = orc3.Params3(nx=nx, ny=ny, nz=nz, tau=(w["tau"], w["tau"]), G=w["G"], g=gg)
     f = orc3.fill_equilibrium(p, rA, rB)
     orc3.run_inplace(p, f, 2)
@@ -193,6 +200,10 @@ def test_3d_bench_size_two_steps(lb3):
         err = _rel(mg[k], mo[k])
         print(f"[case] {k} max rel err {err:.3e}", flush=True)
         assert err <= TOL, k
+    for k in ("rhoA", "rhoB"):
+        err = _rel(m32[k], mo[k])
+        print(f"[case] FP32 {k} max rel err {err:.3e}", flush=True)
+        assert err <= 1e-6, k
 
 
 def test_3d_non_finite_state_is_reported(lb3):
