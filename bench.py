@@ -213,7 +213,7 @@ def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
             "config": "4x1024x512 + 8x2048x1024 + 4x4096x2048, G alternating 0.5 / 1.5, seeds 100-115"}
 
 
-def main() -> int:
+def parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
@@ -228,7 +228,11 @@ def main() -> int:
     ap.add_argument("--d3q19-only", action="store_true",
                     help="time only the 3D (D3Q19) step on 384^3 in --storage (for kernel traces)")
     ap.add_argument("--two-pass", action="store_true", help="with --d3q19-only: the two-pass 3D step")
-    args = ap.parse_args()
+    return ap
+
+
+def main() -> int:
+    args = parser().parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the step shards across GPUs "
               "as described in the design notes, but this implementation runs on a single MI355X.", file=sys.stderr)

@@ -92,3 +92,34 @@ def test_sq_summary_arithmetic(tmp_path):
     assert s["cycles"] == pytest.approx(20.0 * 2 / 8)
     assert s["valu_busy"] == pytest.approx(2560.0 * 2 * 4 / 1024 / (20.0 * 2 / 8))
     assert s["valu_busy_from_insts"] == pytest.approx(7.0 * 2 * 4 / 1024 / (20.0 * 2 / 8))
+
+
+def test_profile_commands_are_current():
+    """Every command a profile summary gives runs committed code with options
+    that exist: bench.py flags parse, profiling subcommands exist, and the
+    programs named are built by build()."""
+    import glob
+    import os
+    import re
+    import shlex
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subs = {"trace", "traffic", "sq", "copy"}
+    seen = 0
+    for md in sorted(glob.glob(os.path.join(root, "profiles", "*.md"))):
+        for line in open(md):
+            if not line.startswith("    ") or line.strip().startswith("|"):
+                continue
+            cmd = re.sub(r"<[^>]*>", "X", line.strip().rstrip("\\").strip())
+            if "python bench.py" in cmd:
+                args = shlex.split(cmd.split("python bench.py", 1)[1])
+                bench.parser().parse_args(args)
+                seen += 1
+            elif "python -m paper_2101_04847_amd.profiling" in cmd:
+                assert cmd.split("python -m paper_2101_04847_amd.profiling", 1)[1].split()[0] in subs, (md, cmd)
+                seen += 1
+            elif cmd.startswith("./"):
+                exe = cmd.split()[0][2:]
+                assert exe == "paper_2101_04847_amd/bw_probe", (md, cmd)
+                assert os.path.exists(os.path.join(root, "paper_2101_04847_amd", "csrc", "bw_probe.hip"))
+                seen += 1
+    assert seen >= 20
