@@ -97,3 +97,36 @@ def test_production_size_wetting_walls_three_steps():
         err = np.max(np.abs(fg[k] - mo[k])) / np.max(np.abs(mo[k]))
         print(f"[case] {k} max rel err {err:.3e}", flush=True)
         assert err <= 1e-12, k
+
+
+def test_paper_parameters_full_size_three_steps():
+    """The configuration of the paper-parameter runs (10000 x 5000, tau = 0.53,
+    G = 0.1381, g = 9e-6, a white-noise interface of amplitude 4 on a tanh
+    profile of the paper's bulk densities 1.0 / 0.1), pass and band chosen by
+    timing: three steps, every density and velocity against the oracle."""
+    import torch
+    from paper_2101_04847_amd import lb
+    nx, ny, tau, G, g = 10000, 5000, 0.53, 0.1381, 9e-6
+    print("[case] full size, paper parameters", nx, ny, tau, G, g, flush=True)
+    yp = np.linspace(-30.0, 30.0, 241)
+    s = 0.5 * (1.0 + np.tanh(yp / 2.0))
+    rA, rB = inputs.profile_densities(nx, ny, inputs.white_noise_height(nx, ny, 9, 4.0), yp,
+                                      0.1 + 0.9 * s, 0.1 + 0.9 * (1.0 - s))
+    gg = ((0.0, -g), (0.0, g))
+    m = lb.Member(nx, ny, rA, rB, tau=(tau, tau), G=G, g=gg)
+    lat = lb.Lattice([m], storage=lb.F64, graph_chunk=2)
+    print("[case] steps per pass", lat.steps_per_pass, "tile shape", lat.tile_shape(), flush=True)
+    lat.step(3)
+    fg = {k: v.cpu().numpy() for k, v in lat.fields(0).items()}
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    p = oracle.Params(nx=nx, ny=ny, tau=(tau, tau), G=G, g=gg)
+    f = oracle.fill_equilibrium(p, rA, rB)
+    oracle.run_inplace(p, f, 3)
+    mo = oracle.macro(p, f)
+    del f
+    for k in ("rhoA", "rhoB", "ux", "uy"):
+        err = np.max(np.abs(fg[k] - mo[k])) / np.max(np.abs(mo[k]))
+        print(f"[case] {k} max rel err {err:.3e}", flush=True)
+        assert err <= 1e-12, k
