@@ -53,6 +53,8 @@ extern "C" {
 #define LB_EHIP (-3)        /* a HIP runtime call failed (message holds its error string) */
 #define LB_ESTATE (-4)      /* handle unknown or already destroyed */
 #define LB_ENONFINITE (-5)  /* lb_diagnostics found a NaN or Inf density or velocity */
+#define LB_EINTERNAL (-6)   /* an algorithm of the library did not complete (message says
+                               which); no HIP call failed */
 
 /* Forcing scheme.  LB_FORCE_SHIFT is the paper's velocity shift inside the
  * equilibrium (Eq. 2-3).  LB_FORCE_GUO is Guo's forcing (Guo, Zheng and Shi,
@@ -182,6 +184,27 @@ int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, doubl
  * (after filling *out) if a density or velocity is not finite. */
 int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profile);
 
+/* Width of the mixing layer of member m at time t.  Sec. 3 follows the
+ * growth of the layer between the two pure phases; its width is taken here
+ * as the integral measure over the rows j of the trimmed domain D
+ *   h = sum_j 6 c_j (1 - c_j),  c_j = clamp((phibar_j - lo) / (hi - lo), 0, 1),
+ * with phibar_j the mean of phi = rho_A - rho_B over row j (the profile of
+ * lb_diagnostics) and lo, hi the bulk references: phibar at the first and the
+ * last row of D (rows diag_trim and ny - diag_trim - 1).  c_j is the fraction
+ * of the phase that starts at the top; a pure row adds 0, a linear ramp of c
+ * over m rows m + 1/(2m), a tanh profile of width w about 3w. */
+typedef struct lb_mixing {
+    int64_t t;
+    double width;            /* h */
+    double bulk_ref[2];      /* the lo, hi used */
+} lb_mixing;
+
+/* Mixing width of member m (see lb_mixing) into *out (host).  ref (host, two
+ * doubles lo, hi) gives the bulk references; NULL takes those recorded by
+ * lb_init from the initial state (t = 0).  LB_EINVAL if they are not finite
+ * or equal.  Uses the workspace field buffer.  Synchronises the stream. */
+int32_t lb_mixing_width(lb_handle *h, int32_t m, const double *ref, lb_mixing *out);
+
 /* Terms of the kinetic-energy balance (Sec. 3, Eq. 17) of member m at time t,
  * averaged like lb_diag over the trimmed domain D, from the fields of
  * lb_fields by centred differences (d_x q = (q(x+1) - q(x-1))/2, x periodic;
@@ -232,7 +255,8 @@ typedef struct lb_topology {
 
 /* Component counts of member m (see lb_topology) into *out (host).  Uses
  * the workspace field buffer (the densities and 4 B per site of D for the
- * union-find parents).  Synchronises the stream. */
+ * union-find parents).  Synchronises the stream.  LB_EINTERNAL if the
+ * labelling left neighbouring sites of one phase in different components. */
 int32_t lb_components(lb_handle *h, int32_t m, lb_topology *out);
 
 /* Populations f(t) of member m, decoded to FP64, into a caller device buffer

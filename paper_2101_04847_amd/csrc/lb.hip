@@ -295,6 +295,7 @@ struct lb_handle {
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipGraph_t graph_src[2] = {nullptr, nullptr};
     int device = 0;
+    std::vector<double> bulk_ref;   // per member: phibar at rows diag_trim and ny - diag_trim - 1 at t = 0
 };
 
 namespace {
@@ -600,6 +601,60 @@ void set_scales(const lb_config *c, const lb_member &mm, Member &M)
     }
 }
 
+// Field pass of member m (rho_A, rho_B, u_x, u_y of f(t) into device
+// buffers; any may be null).  Asynchronous.
+int32_t enqueue_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, double *d_ux, double *d_uy)
+{
+    const Member &M = h->dm[m];
+    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->kbc, tx_index(h->tile_x), true);
+    FieldOut fo{d_rhoA, d_rhoB, d_ux, d_uy};
+    const int64_t n_items = M.item_end - M.item_begin;
+    hipLaunchKernelGGL(fn, dim3((unsigned)n_items), dim3(h->tile_x), 0, h->stream, (const Member *)dev_members(h),
+                       (int)h->dm.size(), M.item_begin, n_items, h->cur, fo);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+// Field pass of member m into the workspace field buffer, then the per-row
+// partial sums and their totals: red[0..RED_NQ) and the row profile of phi at
+// red + RED_NQ.  Asynchronous.
+int32_t enqueue_reductions(lb_handle *h, int32_t m)
+{
+    const Member &M = h->dm[m];
+    const lb_member &mm = h->mem[m];
+    const int64_t n = (int64_t)M.nx * M.ny;
+    double *fld = (double *)(h->ws + h->L.fields);
+    int32_t rc = enqueue_fields(h, m, fld, fld + n, fld + 2 * n, fld + 3 * n);
+    if (rc) return rc;
+    double *part = (double *)(h->ws + h->L.part);
+    double *red = (double *)(h->ws + h->L.red);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(M.ny), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
+                       h->cfg.diag_trim, mm.g[0][0], mm.g[0][1], mm.g[1][0], mm.g[1][1], part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, M.nx, M.ny, red,
+                       red + RED_NQ);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+// The bulk references of the mixing width: phibar at the first and the last
+// row of the trimmed domain, from the current state of every member.
+int32_t record_bulk_refs(lb_handle *h)
+{
+    const int trim = h->cfg.diag_trim;
+    h->bulk_ref.assign(2 * h->dm.size(), 0.0);
+    double *prof = (double *)(h->ws + h->L.red) + RED_NQ;
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        int32_t rc = enqueue_reductions(h, (int32_t)m);
+        if (rc) return rc;
+        const int ny = h->dm[m].ny;
+        HIP_TRY(hipMemcpyAsync(&h->bulk_ref[2 * m], prof + trim, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(&h->bulk_ref[2 * m + 1], prof + (ny - trim - 1), sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    return LB_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -704,6 +759,7 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
         mm.rhoB0 = nullptr;
     }
     if ((rc = choose_tiles(h))) return bail(rc);
+    if ((rc = record_bulk_refs(h))) return bail(rc);
     if ((rc = build_graphs(h))) return bail(rc);
     if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(fail(LB_EHIP, "stream synchronisation failed"));
     {
@@ -738,14 +794,7 @@ int32_t lb_fields(lb_handle *h, int32_t m, double *d_rhoA, double *d_rhoB, doubl
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
-    const Member &M = h->dm[m];
-    StepFn fn = pick_step(h->cfg.storage, h->cfg.forcing, h->kbc, tx_index(h->tile_x), true);
-    FieldOut fo{d_rhoA, d_rhoB, d_ux, d_uy};
-    const int64_t n_items = M.item_end - M.item_begin;
-    hipLaunchKernelGGL(fn, dim3((unsigned)n_items), dim3(h->tile_x), 0, h->stream, (const Member *)dev_members(h),
-                       (int)h->dm.size(), M.item_begin, n_items, h->cur, fo);
-    HIP_TRY(hipGetLastError());
-    return LB_OK;
+    return enqueue_fields(h, m, d_rhoA, d_rhoB, d_ux, d_uy);
 }
 
 int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profile)
@@ -754,18 +803,9 @@ int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profil
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
     if (!out) return fail(LB_EINVAL, "out is NULL");
     const Member &M = h->dm[m];
-    const lb_member &mm = h->mem[m];
-    const int64_t n = (int64_t)M.nx * M.ny;
-    double *fld = (double *)(h->ws + h->L.fields);
-    int32_t rc = lb_fields(h, m, fld, fld + n, fld + 2 * n, fld + 3 * n);
-    if (rc) return rc;
-    double *part = (double *)(h->ws + h->L.part);
     double *red = (double *)(h->ws + h->L.red);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(M.ny), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
-                       h->cfg.diag_trim, mm.g[0][0], mm.g[0][1], mm.g[1][0], mm.g[1][1], part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, M.nx, M.ny, red,
-                       red + RED_NQ);
-    HIP_TRY(hipGetLastError());
+    int32_t rc = enqueue_reductions(h, m);
+    if (rc) return rc;
     std::vector<double> host((size_t)RED_NQ + (phi_profile ? (size_t)M.ny : 0));
     HIP_TRY(hipMemcpyAsync(host.data(), red, host.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -782,6 +822,32 @@ int32_t lb_diagnostics(lb_handle *h, int32_t m, lb_diag *out, double *phi_profil
     if (phi_profile) std::memcpy(phi_profile, host.data() + RED_NQ, (size_t)M.ny * sizeof(double));
     if (!out->finite) return fail(LB_ENONFINITE, "member %d: %.0f non-finite densities or velocities at t = %lld", m,
                                   host[8], (long long)h->t);
+    return LB_OK;
+}
+
+int32_t lb_mixing_width(lb_handle *h, int32_t m, const double *ref, lb_mixing *out)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    const double lo = ref ? ref[0] : h->bulk_ref[2 * m], hi = ref ? ref[1] : h->bulk_ref[2 * m + 1];
+    if (!std::isfinite(lo) || !std::isfinite(hi) || lo == hi)
+        return fail(LB_EINVAL, "member %d: bulk references %g and %g must be finite and differ", m, lo, hi);
+    const Member &M = h->dm[m];
+    int32_t rc = enqueue_reductions(h, m);
+    if (rc) return rc;
+    double *red = (double *)(h->ws + h->L.red);
+    // the width goes to red[RED_NQ - 1] (the non-finite count, not needed here)
+    hipLaunchKernelGGL(k_mixing_width, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)(red + RED_NQ),
+                       M.ny, h->cfg.diag_trim, lo, hi, red + RED_NQ - 1);
+    HIP_TRY(hipGetLastError());
+    double w = 0.0;
+    HIP_TRY(hipMemcpyAsync(&w, red + RED_NQ - 1, sizeof w, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    out->t = h->t;
+    out->width = w;
+    out->bulk_ref[0] = lo;
+    out->bulk_ref[1] = hi;
     return LB_OK;
 }
 
@@ -889,7 +955,7 @@ int32_t lb_components(lb_handle *h, int32_t m, lb_topology *out)
     double host[3];
     HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (host[2] != 0.0) return fail(LB_EHIP, "component labelling left %.0f edges unjoined", host[2]);
+    if (host[2] != 0.0) return fail(LB_EINTERNAL, "component labelling left %.0f edges unjoined", host[2]);
     out->t = h->t;
     out->components[0] = (int64_t)host[0];
     out->components[1] = (int64_t)host[1];

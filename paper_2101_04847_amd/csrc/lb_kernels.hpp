@@ -1475,4 +1475,24 @@ k_reduce_final(const double *__restrict__ part, int nx, int ny, double *__restri
     }
 }
 
+// Integral width of the mixing layer from the row profile of phi (Sec. 3
+// follows the layer's growth; the width is read as the integral measure):
+// c_j = clamp((phibar_j - lo) / (hi - lo), 0, 1) is the fraction of the
+// phase that starts at the top, with lo, hi the bulk values of phibar, and
+// out[0] = sum over the rows of D of 6 c_j (1 - c_j).  One workgroup.
+__global__ void __launch_bounds__(RED_THREADS)
+k_mixing_width(const double *__restrict__ prof, int ny, int trim, double lo, double hi, double *__restrict__ out)
+{
+    __shared__ double sh[RED_THREADS / 64];
+    double a = 0.0;
+    for (int y = trim + (int)threadIdx.x; y < ny - trim; y += RED_THREADS) {
+        double c = (prof[y] - lo) / (hi - lo);
+        if (c < 0.0) c = 0.0;            // comparisons, so that a NaN row stays NaN
+        else if (c > 1.0) c = 1.0;
+        a += 6.0 * c * (1.0 - c);
+    }
+    const double r = block_combine<false>(a, sh);
+    if (threadIdx.x == 0) out[0] = r;
+}
+
 }  // namespace lbk

@@ -22,7 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 # constants of lb.h
-LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_ESTATE, LB_ENONFINITE, LB_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 FORCE_SHIFT, FORCE_GUO = 0, 1
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 WALLS, PERIODIC_Y = 0, 1
@@ -69,6 +69,10 @@ class LbInterface(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("crossings", ctypes.c_int64 * 4), ("length", ctypes.c_double)]
 
 
+class LbMixing(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int64), ("width", ctypes.c_double), ("bulk_ref", ctypes.c_double * 2)]
+
+
 class LbTopology(ctypes.Structure):
     _fields_ = [("t", ctypes.c_int64), ("components", ctypes.c_int64 * 2)]
 
@@ -85,6 +89,8 @@ _lib.lb_fields.argtypes = [_h, ctypes.c_int32] + [ctypes.c_void_p] * 4
 _lib.lb_fields.restype = ctypes.c_int32
 _lib.lb_diagnostics.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbDiag), _dp]
 _lib.lb_diagnostics.restype = ctypes.c_int32
+_lib.lb_mixing_width.argtypes = [_h, ctypes.c_int32, _dp, ctypes.POINTER(LbMixing)]
+_lib.lb_mixing_width.restype = ctypes.c_int32
 _lib.lb_energy_budget.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbBudget)]
 _lib.lb_energy_budget.restype = ctypes.c_int32
 _lib.lb_interface_length.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbInterface)]
@@ -108,7 +114,8 @@ _lib.lb_destroy.restype = ctypes.c_int32
 _lib.lb_last_error.argtypes = []
 _lib.lb_last_error.restype = ctypes.c_char_p
 
-EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_energy_budget",
+EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_mixing_width",
+           "lb_energy_budget",
            "lb_interface_length", "lb_components",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
            "lb_steps_per_pass", "lb_storage_scale", "lb_destroy", "lb_last_error")
@@ -274,6 +281,14 @@ class Lattice:
             out["phi_profile"] = prof
         return out
 
+    def mixing_width(self, m: int = 0, ref=None) -> dict:
+        """Integral width of the mixing layer (lb_mixing): ``width`` and the
+        bulk references ``lo``, ``hi`` used (by default those of t = 0)."""
+        r = LbMixing()
+        rr = None if ref is None else (ctypes.c_double * 2)(float(ref[0]), float(ref[1]))
+        _check(_lib.lb_mixing_width(self._h, m, rr, ctypes.byref(r)), "lb_mixing_width")
+        return {"t": r.t, "width": r.width, "lo": r.bulk_ref[0], "hi": r.bulk_ref[1]}
+
     def energy_budget(self, m: int = 0) -> dict:
         """Terms of the kinetic-energy balance (lb_budget): pb, korteweg,
         ktau, viscous, eta, buoyancy and t."""
@@ -332,11 +347,3 @@ class Lattice:
     def __exit__(self, *a):
         self.close()
 
-
-def mixing_width(phi_profile: np.ndarray, phi_ref: float, trim: int = 10) -> float:
-    """Integral mixing width h = sum_j 6 c_j (1 - c_j) over the rows of the
-    trimmed domain, with the concentration c_j = clamp((1 + phi_j/phi_ref)/2)
-    (host-side analysis of the row profile returned by diagnostics)."""
-    p = np.asarray(phi_profile, dtype=np.float64)[trim:len(phi_profile) - trim]
-    c = np.clip(0.5 * (1.0 + p / phi_ref), 0.0, 1.0)
-    return float(np.sum(6.0 * c * (1.0 - c)))

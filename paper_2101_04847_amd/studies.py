@@ -55,13 +55,6 @@ def _rel_l2(a, b):
     return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b * b)))
 
 
-def phi_reference(profile0, trim=TRIM):
-    """Half the jump of the row-mean order parameter between the bulk rows
-    just inside the trimmed domain at t = 0."""
-    p = np.asarray(profile0)
-    return 0.5 * abs(p[len(p) - trim - 1] - p[trim])
-
-
 def fp32_vs_fp64_large(lb, inputs, stream, log, steps=2000):
     wl = inputs.LARGE_10000x5000
     fields = {}
@@ -99,21 +92,17 @@ def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0), b
     if budget:
         keys += list(BUDGET_KEYS) + ["length", "comp_A", "comp_B"]
     out = [{k: [] for k in keys} for _ in range(n)]
-    phi_refs = []
-    for m in range(n):
-        d = lat.diagnostics(m, profile=True)
-        phi_refs.append(phi_reference(d["phi_profile"]))
     t0 = time.perf_counter()
     for t in range(0, steps + 1, every):
         if t:
             lat.step(every)
         for m, wl in enumerate(wls):
-            d = lat.diagnostics(m, profile=True, check_finite=False)
+            d = lat.diagnostics(m, check_finite=False)
             s = out[m]
             s["t"].append(t)
             for k in ("mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2"):
                 s[k].append(d[k])
-            s["h"].append(lb.mixing_width(d["phi_profile"], phi_refs[m], TRIM))
+            s["h"].append(lat.mixing_width(m)["width"])
             if budget:
                 b = lat.energy_budget(m)
                 for k in BUDGET_KEYS:
@@ -326,13 +315,12 @@ def paper_runs(lb, inputs, stream, log, case="immiscible", members=5, seed0=0, s
     keys = ("t", "Ek", "Ep", "buoyancy", "omega2", "pb", "korteweg", "ktau", "viscous", "eta", "length",
             "comp_A", "comp_B", "h", "mass_A", "mass_B", "umax")
     ser = [{k: [] for k in keys} for _ in range(members)]
-    phi_refs = [phi_reference(lat.diagnostics(m, profile=True)["phi_profile"]) for m in range(members)]
     t0 = time.perf_counter()
     for t in range(0, steps + 1, every):
         if t:
             lat.step(every)
         for m in range(members):
-            d = lat.diagnostics(m, profile=True, check_finite=False)
+            d = lat.diagnostics(m, check_finite=False)
             b = lat.energy_budget(m)
             il = lat.interface_length(m)
             c = lat.components(m)
@@ -345,7 +333,7 @@ def paper_runs(lb, inputs, stream, log, case="immiscible", members=5, seed0=0, s
             s["length"].append(il["length"])
             s["comp_A"].append(c["A"])
             s["comp_B"].append(c["B"])
-            s["h"].append(lb.mixing_width(d["phi_profile"], phi_refs[m], TRIM))
+            s["h"].append(lat.mixing_width(m)["width"])
         if t and t % (10 * every) == 0:
             log(f"paper runs {case}: t = {t} ({time.perf_counter() - t0:.0f} s)")
     _close(lat)

@@ -36,6 +36,7 @@ def test_header_constants_match_binding(lb):
     assert consts["LB_OK"] == lb.LB_OK and consts["LB_EINVAL"] == lb.LB_EINVAL
     assert consts["LB_ENOMEM"] == lb.LB_ENOMEM and consts["LB_EHIP"] == lb.LB_EHIP
     assert consts["LB_ESTATE"] == lb.LB_ESTATE and consts["LB_ENONFINITE"] == lb.LB_ENONFINITE
+    assert consts["LB_EINTERNAL"] == lb.LB_EINTERNAL
     assert (consts["LB_F64"], consts["LB_F32"], consts["LB_F16S"], consts["LB_BF16S"]) == (0, 1, 2, 3)
     assert (consts["LB_FORCE_SHIFT"], consts["LB_FORCE_GUO"]) == (0, 1)
     assert (consts["LB_WALLS"], consts["LB_PERIODIC_Y"]) == (0, 1)
@@ -48,6 +49,7 @@ def test_header_constants_match_binding(lb):
     assert ctypes.sizeof(lb.LbBudget) == 8 + 6 * 8
     assert ctypes.sizeof(lb.LbInterface) == 8 + 4 * 8 + 8
     assert ctypes.sizeof(lb.LbTopology) == 8 + 2 * 8
+    assert ctypes.sizeof(lb.LbMixing) == 8 + 3 * 8
 
 
 def _member(lb, nx=32, ny=30, **kw):

@@ -1,0 +1,82 @@
+"""GPU mixing width (lb_mixing_width) against the oracle's (oracle/mixing.py,
+pinned by closed forms in test_oracle_mixing.py) on the same states."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mixing
+from paper_2101_04847_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2101_04847_amd import lb as mod
+    return mod
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("nx,ny,seed,G,g,steps", [
+    (128, 64, None, 1.5, 1e-5, (0, 100, 400)),        # the 128 x 64 workload, one cosine mode
+    (300, 140, 5, 0.5, 1e-4, (0, 250, 600)),          # miscible, 32 seeded modes, strong gravity
+    (200, 96, 9, 1.5, 2e-4, (0, 301, 900)),           # immiscible, odd step counts
+])
+def test_mixing_width_matches_oracle(lb, nx, ny, seed, G, g, steps):
+    _say("mixing width", nx, ny, seed, G, g)
+    rA, rB = inputs.single_mode(nx, ny, 2.0) if seed is None else inputs.multi_mode(nx, ny, seed)
+    gg = ((0.0, -g), (0.0, g))
+    lat = lb.Lattice([lb.Member(nx, ny, rA, rB, tau=(1.0, 1.0), G=G, g=gg)], storage=lb.F64, diag_trim=10)
+    p = oracle.Params(nx=nx, ny=ny, tau=(1.0, 1.0), G=G, g=gg)
+    f = oracle.fill_equilibrium(p, rA, rB)
+    lo, hi = mixing.bulk_reference(oracle.diagnostics(p, f, trim=10, profile=True)["phi_profile"], 10)
+    t = 0
+    for target in steps:
+        f = oracle.run(p, f, target - t)
+        lat.step(target - t)
+        t = target
+        prof = oracle.diagnostics(p, f, trim=10, profile=True)["phi_profile"]
+        h_orc = mixing.mixing_width(prof, lo, hi, 10)
+        r = lat.mixing_width(0)
+        assert r["t"] == t
+        # the references recorded at t = 0 are the oracle's bulk rows
+        assert abs(r["lo"] - lo) <= 1e-12 and abs(r["hi"] - hi) <= 1e-12
+        # profiles agree to 1e-12 per row; each row's term 6 c (1 - c) has a
+        # slope of at most 6 / |hi - lo| in phibar
+        bound = (ny - 20) * 6.0 / abs(hi - lo) * 2e-12 + 1e-13 * max(h_orc, 1.0)
+        assert abs(r["width"] - h_orc) <= bound, (t, r["width"], h_orc)
+        # explicit references give the same reduction
+        r2 = lat.mixing_width(0, ref=(lo, hi))
+        assert r2["width"] == r["width"]
+        print(f"t = {t}: width gpu {r['width']:.12f} oracle {h_orc:.12f}", flush=True)
+    lat.close()
+
+
+def test_mixing_width_per_member_and_errors(lb):
+    """Each ensemble member keeps its own references; equal or non-finite
+    references are rejected."""
+    _say("mixing width ensemble")
+    mem = []
+    for seed, ny in ((3, 80), (4, 120)):
+        rA, rB = inputs.multi_mode(150, ny, seed)
+        mem.append(lb.Member(150, ny, rA, rB, tau=(1.0, 1.0), G=1.5, g=((0.0, -1e-4), (0.0, 1e-4))))
+    ens = lb.Lattice(mem, storage=lb.F64, diag_trim=10)
+    solo = lb.Lattice([mem[1]], storage=lb.F64, diag_trim=10)
+    ens.step(120)
+    solo.step(120)
+    a, b = ens.mixing_width(1), solo.mixing_width(0)
+    assert (a["width"], a["lo"], a["hi"]) == (b["width"], b["lo"], b["hi"])
+    assert ens.mixing_width(0)["width"] != a["width"]
+    with pytest.raises(lb.LBError) as e:
+        ens.mixing_width(0, ref=(0.3, 0.3))
+    assert e.value.code == lb.LB_EINVAL
+    with pytest.raises(lb.LBError) as e:
+        ens.mixing_width(0, ref=(float("nan"), 1.0))
+    assert e.value.code == lb.LB_EINVAL
+    ens.close()
+    solo.close()

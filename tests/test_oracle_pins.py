@@ -154,9 +154,11 @@ def test_potential_energy_mass_and_buoyancy_closed_forms(orc):
     rB = np.full((ny, nx), c)
     p = orc.Params(nx=nx, ny=ny, tau=(1.0, 1.0), G=0.0, g=((0.0, -g), (0.0, g)))
     f = orc.fill_equilibrium(p, rA, rB)
-    d = orc.diagnostics(p, f, trim=trim)
+    d = orc.diagnostics(p, f, trim=trim, profile=True)
     m = ny - 2 * trim
     assert d["Ep"] == pytest.approx(g * b * (m * m - 1) / 12.0, rel=1e-12)
+    # row profile of phi = rho_A - rho_B over every row (trimmed ones too)
+    assert np.max(np.abs(d["phi_profile"] - (a + b * yj - c))) <= 1e-14
     assert d["mass_A"] == pytest.approx(a * nx * ny, rel=1e-14)
     assert d["mass_B"] == pytest.approx(c * nx * ny, rel=1e-14)
     phi = (a + b * yj - c)[trim:ny - trim]
@@ -187,6 +189,36 @@ def test_enstrophy_and_kinetic_energy_taylor_green(orc, n, N):
     assert d["Ek"] == pytest.approx(U * U / 4, rel=1e-12)
     assert d["umax"] <= U * (1 + 1e-12)
     assert d["finite"]
+
+
+@pytest.mark.parametrize("U,V", [(0.03, -0.07), (-0.05, 0.02)])
+def test_max_speed_of_a_uniform_flow(orc, U, V):
+    """A uniform flow u = (U, V) of a uniform mixture (G = 0, g = 0, so
+    u_phys = u): max |u| over the lattice is the speed hypot(U, V), larger
+    than either component, and E_k = rho |u|^2 / 2."""
+    nx, ny = 12, 30
+    p = orc.Params(nx=nx, ny=ny, tau=(0.9, 0.9), periodic_y=True)
+    f = orc.fill_equilibrium(p, np.full((ny, nx), 0.6), np.full((ny, nx), 0.45),
+                             np.full((ny, nx), U), np.full((ny, nx), V))
+    d = orc.diagnostics(p, f, trim=5)
+    speed = float(np.hypot(U, V))
+    assert d["umax"] == pytest.approx(speed, rel=1e-14)
+    assert d["umax"] > max(abs(U), abs(V)) * 1.05
+    assert d["Ek"] == pytest.approx(0.5 * 1.05 * speed * speed, rel=1e-13)
+
+
+def test_max_speed_finds_the_fastest_site(orc):
+    """One site moving at (U, V) in a fluid at rest, placed in a trimmed row:
+    max |u| runs over the whole lattice, not only the trimmed domain."""
+    nx, ny = 10, 26
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    ux[1, 7], uy[1, 7] = -0.02, 0.09
+    ux[13, 3] = 0.05
+    p = orc.Params(nx=nx, ny=ny, tau=(1.0, 1.0), periodic_y=True)
+    f = orc.fill_equilibrium(p, np.full((ny, nx), 0.5), np.full((ny, nx), 0.5), ux, uy)
+    d = orc.diagnostics(p, f, trim=5)
+    assert d["umax"] == pytest.approx(float(np.hypot(0.02, 0.09)), rel=1e-14)
 
 
 def test_diagnostics_flag_non_finite(orc):
