@@ -17,6 +17,16 @@ on a bounded sample of the same workload, the reduced-precision storage
 modes, and the 16-member batched ensemble (4 x 1024x512, 8 x 2048x1024,
 4 x 4096x2048, FP32).
 
+Besides the rates, the line carries the measurements the rates are judged
+by: the density-field error of FP32 storage against FP64 on the headline
+lattice at step 2000; mass drift, mixing-width and density errors of the
+reduced-precision codes on the 4096 x 2048 lattices (miscible and
+immiscible) over 20000 steps against FP64; the 16 ensemble members' errors
+against their FP64 runs and the ensemble means of the mixing width and the
+energy budget; the 2048 x 1024 lattice's rate under both forcing schemes;
+and a plain device copy timed in the same process as a measured roofline
+denominator.
+
     python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s] [--spp 0|1|2]
     python bench.py --report out.json     # precision and ensemble studies
 """
@@ -32,9 +42,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-# 2 components x 9 populations x (read + write) x element size: the bytes
-# one kernel pass moves per site (per lattice update for single steps)
-BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}
+# 2 components x 9 populations x (read + write) x element size, plus in the
+# 16-bit modes the two FP32 site densities (read + write): the bytes one
+# kernel pass moves per site (per lattice update for single steps)
+BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
 KERNEL = {1: "step", 2: "step2"}
 METRIC = "MLUPS + % HBM peak, 2-comp D2Q9 Shan-Chen 10000×5000; ensemble MLUPS"
 
@@ -63,6 +74,63 @@ def measured_traffic(kernel: str, storage: str, nx: int, ny: int, tile=None):
     return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def graph_chunk_for(steps: int) -> int:
+    """Steps per captured graph: 100, or the whole (even) timed run when it
+    is shorter, so that the timed region replays at least one graph."""
+    return 100 if steps >= 100 else max(2, steps - steps % 2)
+
+
+def copy_bandwidth(stream, gbytes: float = 4.0, reps: int = 5) -> dict:
+    """Best plain device-to-device copy (read + write of gbytes each way) over
+    the probe's copy variants and grid sizes, timed with events on `stream`
+    in this process (libbwprobe.so)."""
+    import ctypes
+
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2101_04847_amd", "libbwprobe.so"))
+    lib.bw_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                            ctypes.c_void_p]
+    lib.bw_copy.restype = ctypes.c_int
+    n = int(gbytes * 1e9) // 4096 * 4096
+    a = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    results = []
+    for v in range(lib.bw_copy_variants()):
+        for grid in (2048, 8192, 32768, 65536):
+            def run():
+                rc = lib.bw_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()), n, v, grid, sp)
+                if rc != 0:
+                    raise RuntimeError(f"bw_copy variant {v} grid {grid}: status {rc}")
+            run()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            results.append({"variant": v, "grid": grid, "GBs": round(2 * n / (ms / 1e3) / 1e9, 1)})
+    del a, b
+    torch.cuda.empty_cache()
+    best = max(results, key=lambda r: r["GBs"])
+    return {"GBs": best["GBs"], "variant": best["variant"], "grid": best["grid"], "bytes_each_way": n,
+            "kernel": "bw_copy (paper_2101_04847_amd/csrc/bw_probe.hip)", "candidates": len(results)}
+
+
 def storage_code(lb, name):
     return {"f64": lb.F64, "f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[name]
 
@@ -80,6 +148,13 @@ def hbm_frac(storage, spp, ms_step, sites):
     """Fraction of the published HBM bandwidth that the pass's own bytes
     (every population read and written once per pass) represent."""
     return round(BYTES_PER_LU[storage] * sites / (ms_step * spp / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+
+
+def hbm_frac_single_step_basis(storage, ms_step, sites):
+    """Fraction of the published HBM bandwidth that the single-step method's
+    bytes (every population read and written once per step) would need at
+    this rate; above 1 when two steps share one pass over HBM."""
+    return round(BYTES_PER_LU[storage] * sites / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
 
 def time_steps(lat, steps, warmup, stream, chunk=100, chunks_out=None):
@@ -142,7 +217,7 @@ def cpu_baseline(wl, target_s: float = 40.0) -> dict:
         oracle.set_threads(cores)
     del f
     return {"value": round(wl.nx * wl.ny * n / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{n} steps of the full {wl.nx}x{wl.ny} lattice after 2 untimed steps "
                       f"(FP64, OpenMP over rows, {dt:.1f} s)",
             "single_thread": {"value": round(wl.nx * wl.ny / dt1 / 1e6, 3), "unit": "MLUPS",
@@ -159,7 +234,8 @@ def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0, **walls)
     mlups = sites / (ms / 1e3) / 1e6
     out = {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "steps_per_pass": got,
            "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": BYTES_PER_LU[name] // got,
-           "hbm_frac": hbm_frac(name, got, ms, sites)}
+           "hbm_frac": hbm_frac(name, got, ms, sites),
+           "hbm_frac_single_step_basis": hbm_frac_single_step_basis(name, ms, sites)}
     if walls:
         out["walls"] = {k: list(v) if isinstance(v, tuple) else v for k, v in walls.items()}
     return out
@@ -213,6 +289,172 @@ def ensemble_line(lb, inputs, stream, storage="f32", steps=300, warmup=50):
             "config": "4x1024x512 + 8x2048x1024 + 4x4096x2048, G alternating 0.5 / 1.5, seeds 100-115"}
 
 
+def _rel_l2(a, b) -> float:
+    """||a - b|| / ||b|| of two device tensors, in FP64 on the GPU."""
+    import torch
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def fp32_error_line(lb, inputs, stream, steps=2000):
+    """The headline lattice advanced `steps` steps with FP64 and with FP32
+    storage side by side: relative L2 errors of the density fields, phi and
+    |u|, the largest density difference, and the mixing widths."""
+    import torch
+    wl = inputs.LARGE_10000x5000
+    out = {"workload": wl.name, "step": steps}
+    fields = {}
+    for name in ("f64", "f32"):
+        lat = lattice_for(lb, [wl], storage_code(lb, name), stream=stream)
+        m0 = lat.diagnostics(0)
+        lat.step(steps)
+        fields[name] = lat.fields(0)
+        d = lat.diagnostics(0)
+        out[f"{name}_mass_drift"] = max(abs(d["mass_A"] - m0["mass_A"]) / m0["mass_A"],
+                                        abs(d["mass_B"] - m0["mass_B"]) / m0["mass_B"])
+        out[f"{name}_mixing_width"] = lat.mixing_width(0)["width"]
+        release(lat)
+    a, b = fields["f32"], fields["f64"]
+    out["rel_l2_rhoA"] = _rel_l2(a["rhoA"], b["rhoA"])
+    out["rel_l2_rhoB"] = _rel_l2(a["rhoB"], b["rhoB"])
+    out["rel_l2_phi"] = _rel_l2(a["rhoA"] - a["rhoB"], b["rhoA"] - b["rhoB"])
+    out["rel_l2_speed"] = _rel_l2(torch.hypot(a["ux"], a["uy"]), torch.hypot(b["ux"], b["uy"]))
+    out["max_abs_rho"] = float(max((a["rhoA"] - b["rhoA"]).abs().max(), (a["rhoB"] - b["rhoB"]).abs().max()))
+    del fields, a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def _series_run(lb, wl, storage, stream, steps, every):
+    """One lattice advanced in graph-replayed chunks of `every` steps: the
+    masses and mixing width at every sample, the final densities, and the
+    event-timed step rate (samples excluded)."""
+    import torch
+    lat = lattice_for(lb, [wl], storage, stream=stream, graph_chunk=every)
+    mass, width = [], []
+    ms = 0.0
+    for t in range(0, steps + 1, every):
+        if t:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lat.step(every)
+            e1.record(stream)
+            e1.synchronize()
+            ms += e0.elapsed_time(e1)
+        d = lat.diagnostics(0, check_finite=False)
+        mass.append((d["mass_A"], d["mass_B"]))
+        width.append(lat.mixing_width(0)["width"])
+    f = lat.fields(0)
+    fin = {k: f[k] for k in ("rhoA", "rhoB")}
+    spp = lat.steps_per_pass
+    release(lat)
+    return {"mass": mass, "width": width, "fields": fin, "ms_per_step": ms / steps, "spp": spp,
+            "finite": bool(d["finite"])}
+
+
+def reduced_precision_lines(lb, inputs, stream, steps=20000, every=100):
+    """The 4096 x 2048 lattices (miscible G = 0.5 and immiscible G = 1.5):
+    FP32, FP16S and BF16S storage against the FP64 run of the same lattice
+    over `steps` steps: the largest relative mass drift of either component
+    over the run, the mixing-width error (largest over the samples and at
+    the end), the final relative L2 density error, and the step rate."""
+    import torch
+    res = []
+    for wl in inputs.PRECISION_4096x2048:
+        ref = _series_run(lb, wl, lb.F64, stream, steps, every)
+        h64 = ref["width"]
+        row = {"workload": wl.name, "G_AB": wl.G, "steps": steps, "every": every,
+               "f64": {"MLUPS": round(wl.nx * wl.ny / (ref["ms_per_step"] / 1e3) / 1e6, 1),
+                       "mass_drift": _drift(ref["mass"]), "mixing_width_final": h64[-1]}}
+        for name in ("f32", "f16s", "bf16s"):
+            r = _series_run(lb, wl, storage_code(lb, name), stream, steps, every)
+            h = r["width"]
+            row[name] = {
+                "MLUPS": round(wl.nx * wl.ny / (r["ms_per_step"] / 1e3) / 1e6, 1), "steps_per_pass": r["spp"],
+                "mass_drift": _drift(r["mass"]),
+                "mixing_width_final": h[-1],
+                "mixing_width_rel_err_final": abs(h[-1] - h64[-1]) / abs(h64[-1]),
+                "mixing_width_max_abs_err": max(abs(x - y) for x, y in zip(h, h64)),
+                "rel_l2_rhoA_final": _rel_l2(r["fields"]["rhoA"], ref["fields"]["rhoA"]),
+                "rel_l2_rhoB_final": _rel_l2(r["fields"]["rhoB"], ref["fields"]["rhoB"]),
+                "finite": r["finite"]}
+            del r
+            torch.cuda.empty_cache()
+        del ref
+        torch.cuda.empty_cache()
+        res.append(row)
+    return res
+
+
+def _drift(mass) -> float:
+    """Largest |M_s(t) - M_s(0)| / M_s(0) over the samples and both components."""
+    return max(abs(m[s] - mass[0][s]) / mass[0][s] for m in mass for s in (0, 1))
+
+
+def ensemble_error_line(lb, inputs, stream, steps=1000):
+    """The 16-member ensemble advanced `steps` steps in FP32 and in FP64 (one
+    launch per pass over all members each): per member the relative L2
+    errors of the density fields of FP32 against FP64; ensemble means and
+    spreads (per coupling) of the mixing width and the energy-budget terms of
+    the FP32 run."""
+    import torch
+    wls = inputs.ensemble_16()
+    runs = {}
+    for name in ("f64", "f32"):
+        lat = lattice_for(lb, wls, storage_code(lb, name), stream=stream)
+        lat.step(steps)
+        per = []
+        for k in range(len(wls)):
+            f = lat.fields(k)
+            d = lat.diagnostics(k)
+            b = lat.energy_budget(k)
+            per.append({"rhoA": f["rhoA"], "rhoB": f["rhoB"], "width": lat.mixing_width(k)["width"],
+                        "Ek": d["Ek"], "Ep": d["Ep"], "buoyancy": d["buoyancy"],
+                        **{q: b[q] for q in ("pb", "korteweg", "ktau", "viscous")}})
+        runs[name] = per
+        release(lat)
+    errs = []
+    for k, wl in enumerate(wls):
+        a, b = runs["f32"][k], runs["f64"][k]
+        errs.append({"member": k, "nx": wl.nx, "ny": wl.ny, "G_AB": wl.G,
+                     "rel_l2_rho": max(_rel_l2(a["rhoA"], b["rhoA"]), _rel_l2(a["rhoB"], b["rhoB"])),
+                     "width_rel_err": abs(a["width"] - b["width"]) / abs(b["width"])})
+    groups = {}
+    import statistics
+    for G in sorted({wl.G for wl in wls}):
+        idx = [k for k, wl in enumerate(wls) if wl.G == G]
+        grp = {}
+        for q in ("width", "Ek", "Ep", "buoyancy", "pb", "korteweg", "ktau", "viscous"):
+            v = [runs["f32"][k][q] for k in idx]
+            grp[q] = {"mean": statistics.fmean(v), "std": statistics.pstdev(v)}
+        groups[f"G={G}"] = grp
+    del runs
+    torch.cuda.empty_cache()
+    return {"step": steps, "storage": "f32 vs f64",
+            "rel_l2_rho_max": max(e["rel_l2_rho"] for e in errs),
+            "rel_l2_rho_mean": statistics.fmean(e["rel_l2_rho"] for e in errs),
+            "width_rel_err_max": max(e["width_rel_err"] for e in errs),
+            "members": errs, "ensemble_means_f32": groups}
+
+
+def medium_lines(lb, inputs, stream, steps=1000, warmup=100):
+    """The 2048 x 1024 lattice (FP64) under both forcing schemes: step rate
+    and pass chosen."""
+    out = []
+    wl = inputs.MEDIUM_2048x1024
+    rA, rB = wl.densities()
+    for name, forcing in (("velocity-shift", lb.FORCE_SHIFT), ("guo", lb.FORCE_GUO)):
+        m = lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity)
+        lat = lb.Lattice([m], forcing=forcing, storage=lb.F64, graph_chunk=100, stream=stream)
+        ms, _ = time_steps(lat, steps, warmup, stream)
+        spp, tile = lat.steps_per_pass, lat.tile_shape()
+        release(lat)
+        out.append({"workload": wl.name, "forcing": name, "storage": "f64",
+                    "MLUPS": round(wl.nx * wl.ny / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                    "steps_per_pass": spp, "tile": list(tile),
+                    "hbm_frac": hbm_frac("f64", spp, ms, wl.nx * wl.ny)})
+    return out
+
+
 def parser() -> argparse.ArgumentParser:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,12 +506,21 @@ def main() -> int:
     if args.tile:
         a, b = args.tile.lower().split("x")
         tile = (int(a), int(b))
-    lat = lattice_for(lb, [wl], storage_code(lb, args.storage), tile=tile, stream=stream, spp=args.spp)
+    chunk = graph_chunk_for(args.steps)
+    t_init = time.perf_counter()
+    lat = lattice_for(lb, [wl], storage_code(lb, args.storage), tile=tile, stream=stream, spp=args.spp,
+                      graph_chunk=chunk)
+    t_init = time.perf_counter() - t_init
     tx, th = lat.tile_shape()
     spp = lat.steps_per_pass
-    log(f"{wl.name} storage={args.storage} steps/pass={spp} tile={tx}x{th} warmup={args.warmup} steps={args.steps}")
+    log(f"{wl.name} storage={args.storage} steps/pass={spp} tile={tx}x{th} warmup={args.warmup} steps={args.steps}"
+        f" graph chunk={chunk}")
+    # the warm-up leaves the buffer parity and graph alignment of the timed
+    # region as they are; lb_step replays one graph per full chunk of a call
     chunk_ms = []
-    ms_step, wall = time_steps(lat, args.steps, args.warmup, stream, chunks_out=chunk_ms)
+    ms_step, wall = time_steps(lat, args.steps, args.warmup, stream, chunk=chunk, chunks_out=chunk_ms)
+    replays = (args.steps // chunk) if args.steps >= chunk else 0
+    eager_steps = args.steps - replays * chunk
     d = lat.diagnostics(0)
     # cost of the analysis passes (each call synchronises): energy-budget
     # averages and the kinetic-energy balance terms, best of three
@@ -300,13 +551,25 @@ def main() -> int:
     alg_bytes = BYTES_PER_LU[args.storage] * sites
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
     traffic = measured_traffic(kernel, args.storage, wl.nx, wl.ny, tile=[tx, th])
+    log("measured copy bandwidth")
+    copy = copy_bandwidth(stream)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": alg_bytes, "bytes_per_lu": BYTES_PER_LU[args.storage] // spp,
             "kernel": "lbk::k_" + kernel, "steps_per_launch": spp, "launch_ms": round(launch_ms, 4),
-            # the single-step method's 288 B per update at this rate (above
-            # the HBM peak when two steps are fused)
-            "effective_GBs": round(mlups * 1e6 * BYTES_PER_LU[args.storage] / 1e9, 1)}
+            # counted HBM-side bytes over the algorithmic bytes of one launch
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),
+            # the single-step method's bytes per update (every population
+            # read and written once per step) at this rate: above the HBM
+            # peak when two steps share one pass over the populations
+            "effective_GBs": round(mlups * 1e6 * BYTES_PER_LU[args.storage] / 1e9, 1),
+            "frac_single_step_basis": hbm_frac_single_step_basis(args.storage, ms_step, sites),
+            "frac_basis_note": ("frac counts the launch's own bytes (each population read and written once "
+                                f"per launch of {spp} step(s)); frac_single_step_basis counts "
+                                f"{BYTES_PER_LU[args.storage]} B per update, which two fused steps need not move"),
+            # a plain device copy of 4 GB each way, timed in this process
+            "measured_copy_GBs": copy["GBs"], "frac_of_measured_copy": round(achieved / copy["GBs"], 4),
+            "measured_copy": copy}
 
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
@@ -315,10 +578,11 @@ def main() -> int:
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "tau": wl.tau, "G_AB": wl.G, "g": wl.g,
                    "forcing": "velocity-shift", "storage": args.storage, "steps_per_pass": spp,
-                   "tile": [tx, th], "graph_chunk": 100, "wall_s": round(wall, 3)},
+                   "tile": [tx, th], "graph_chunk": chunk, "graph_replays_timed": replays,
+                   "eager_steps_timed": eager_steps, "lb_init_s": round(t_init, 3), "wall_s": round(wall, 3)},
         "roofline": roof,
         "state_check": {"finite": d["finite"], "umax": d["umax"], "t": d["t"]},
-        # ms per step of each 100-step graph replay inside the timed region
+        # ms per step of each chunk (one graph replay) inside the timed region
         "chunk_ms_per_step": {"median": round(float(sorted(chunk_ms)[len(chunk_ms) // 2]), 4),
                               "min": round(min(chunk_ms), 4), "max": round(max(chunk_ms), 4), "n": len(chunk_ms)},
         "analysis_ms": {"diagnostics": round(min(t_diag) * 1e3, 3), "energy_budget": round(min(t_budget) * 1e3, 3),
@@ -336,8 +600,16 @@ def main() -> int:
             if name != args.storage:
                 log("storage variant", name)
                 out["storage_variants"].append(variant_line(lb, inputs, name, stream))
+        log("FP32 against FP64 at step 2000")
+        out["fp32_error_10000x5000"] = fp32_error_line(lb, inputs, stream)
+        log("reduced precision on 4096x2048, 20000 steps")
+        out["reduced_precision_4096x2048"] = reduced_precision_lines(lb, inputs, stream)
         log("ensemble of 16")
         out["ensemble"] = ensemble_line(lb, inputs, stream)
+        log("ensemble errors")
+        out["ensemble"]["errors"] = ensemble_error_line(lb, inputs, stream)
+        log("2048x1024, both forcings")
+        out["medium_2048x1024"] = medium_lines(lb, inputs, stream)
         # wetting walls (Eq. 6 force, psi = 0 on boundary nodes): the wall-term kernels
         log("wetting walls")
         out["wetting_walls"] = variant_line(lb, inputs, args.storage, stream, G_wall=(0.05, -0.05),

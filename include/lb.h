@@ -66,11 +66,18 @@ extern "C" {
 
 /* Storage of the populations between steps.  Densities, the Shan-Chen force
  * and every diagnostic sum are computed in FP64 in all modes.
- *   LB_F64   FP64 storage, FP64 arithmetic throughout.
- *   LB_F32   FP32 storage, FP32 collision.
- *   LB_F16S  IEEE binary16 storage of q = (f_i - w_i rho0_s) * scale_{s,i}, FP32 collision.
- *   LB_BF16S bfloat16 storage of the same shifted, scaled q, FP32 collision.
- * scale_{s,i} is a power of two chosen at lb_init (see lb_member.rho0). */
+ *   LB_F64   FP64 storage, FP64 arithmetic throughout (144 B per site).
+ *   LB_F32   FP32 storage, FP32 collision (72 B per site).
+ *   LB_F16S  per site and component, the FP32 density rhat_s(x) and IEEE
+ *            binary16 codes q_i = (f*_i - w_i rhat_s) * scale_{s,i} of the
+ *            populations, FP32 collision (44 B per site).
+ *   LB_BF16S the same with bfloat16 codes.
+ * A stored population decodes as f*_i = w_i rhat_s(x) + q_i / scale_{s,i}: the
+ * codes hold only each population's departure from w_i times its own site's
+ * density (the velocity and non-equilibrium parts), and rhat_s is set when
+ * the codes are written so that the decoded populations of a site sum to its
+ * density, so rounding the codes changes no component's mass.
+ * scale_{s,i} is a power of two chosen at lb_init (lb_storage_scale). */
 #define LB_F64 0
 #define LB_F32 1
 #define LB_F16S 2
@@ -102,9 +109,7 @@ typedef struct lb_member {
                                 Eq. 7 is g[0] = {0, -g~}, g[1] = {0, +g~} */
     const double *rhoA0;     /* host, [ny][nx]: initial densities; f(0) = w_i rho_s */
     const double *rhoB0;
-    double rho0[2];          /* LB_F16S / LB_BF16S only: reference densities of the
-                                shift w_i rho0_s; 0 selects the mean initial density,
-                                a negative value stores f_i unshifted */
+    double reserved2[2];     /* must be 0 */
     double G_wall[2];        /* fluid-boundary couplings G_Ab, G_Bb of Eq. 6 (finite;
                                 used with LB_WALLS): row 0 gets the acceleration
                                 +G_sb/6 and row ny-1 -G_sb/6 along y (exactly
@@ -281,9 +286,10 @@ int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *t
 int32_t lb_steps_per_pass(const lb_handle *h);
 
 /* Storage scale of member m for the 16-bit modes: scale[s*9 + i] receives
- * scale_{s,i} and shift[s*9 + i] receives w_i rho0_s (host arrays of 18;
- * either may be NULL).  In LB_F64 / LB_F32 the scales are 1 and shifts 0. */
-int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *shift);
+ * scale_{s,i} and weight[s*9 + i] the factor w_i (rounded to FP32) of the
+ * per-site shift w_i rhat_s(x) (host arrays of 18; either may be NULL).  In
+ * LB_F64 / LB_F32 the scales are 1 and the weights 0. */
+int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *weight);
 
 /* Destroy a handle: waits for its stream, frees graphs and host state.  The
  * workspace stays with the caller.  Later calls with h return LB_ESTATE. */

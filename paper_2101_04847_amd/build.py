@@ -13,6 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblb.so")
 PROBE = os.path.join(PKG, "bw_probe")
+PROBE_LIB = os.path.join(PKG, "libbwprobe.so")
 SOURCES = [os.path.join(CSRC, "lb.hip"), os.path.join(CSRC, "lb3.hip")]
 HEADERS = [os.path.join(CSRC, "lb_kernels.hpp"), os.path.join(CSRC, "lb_internal.hpp"),
            os.path.join(CSRC, "lb_memory.hpp"),
@@ -51,15 +52,17 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed building liblb.so")
     _report_warnings(res.stderr)
     os.replace(tmp, LIB)
-    # the bandwidth probe (measured roofline denominator)
-    tmp = PROBE + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-o", tmp, os.path.join(CSRC, "bw_probe.hip")]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building bw_probe")
-    os.replace(tmp, PROBE)
+    # the bandwidth probe (measured roofline denominator): a shared library
+    # for in-process use by the benchmark and a stand-alone program
+    for out, extra in ((PROBE_LIB, ["-fPIC", "-shared"]), (PROBE, ["-DBW_PROBE_MAIN"])):
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+               "-packed-fp32-ops", *extra, "-o", tmp, os.path.join(CSRC, "bw_probe.hip")]
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed building " + os.path.basename(out))
+        os.replace(tmp, out)
     return LIB
 
 

@@ -59,6 +59,15 @@ size_t elem_bytes(int storage)
 
 int64_t pitch_of(int nx) { return (int64_t)align_up((size_t)nx, 64); }
 
+bool site_shift(int storage) { return storage == LB_F16S || storage == LB_BF16S; }
+
+// Bytes of one row block: 2 x 9 population segments of pitch elements, plus
+// (16-bit modes) the two FP32 site-density segments.
+int64_t row_bytes_of(int storage, int64_t pitch)
+{
+    return (int64_t)2 * NQ * pitch * (int64_t)elem_bytes(storage) + (site_shift(storage) ? 2 * 4 * pitch : 0);
+}
+
 // ---------------------------------------------------------------------------
 // Kernel dispatch tables.
 using StepFn = void (*)(const Member *, int, int64_t, int64_t, int, FieldOut);
@@ -192,11 +201,10 @@ bool build_layout(const lb_config *c, Layout &L)
     L.members = off;
     off = align_up(off + sizeof(Member) * (size_t)c->n_members, ALIGN);
     int64_t max_sites = 0, max_ny = 0;
-    const size_t eb = elem_bytes(c->storage);
     for (int b = 0; b < 2; ++b) L.fbuf[b].resize(c->n_members);
     for (int m = 0; m < c->n_members; ++m) {
         const lb_member &mm = c->members[m];
-        const size_t bytes = (size_t)2 * NQ * (size_t)mm.ny * (size_t)pitch_of(mm.nx) * eb;
+        const size_t bytes = (size_t)mm.ny * (size_t)row_bytes_of(c->storage, pitch_of(mm.nx));
         for (int b = 0; b < 2; ++b) {
             L.fbuf[b][m] = off;
             off = align_up(off + bytes, ALIGN);
@@ -250,7 +258,7 @@ int32_t validate(const lb_config *c)
         if (mm.nx < 3 || mm.ny < 3) return fail(LB_EINVAL, "member %d: nx = %d, ny = %d must be >= 3", m, mm.nx, mm.ny);
         if ((int64_t)mm.nx * mm.ny > ((int64_t)1 << 31))
             return fail(LB_EINVAL, "member %d: %d x %d sites exceed 2^31", m, mm.nx, mm.ny);
-        if ((int64_t)2 * NQ * pitch_of(mm.nx) * (int64_t)elem_bytes(c->storage) > (int64_t)INT32_MAX)
+        if (row_bytes_of(c->storage, pitch_of(mm.nx)) > (int64_t)INT32_MAX)
             return fail(LB_EINVAL, "member %d: a row block of nx = %d exceeds 2^31 bytes", m, mm.nx);
         for (int s = 0; s < 2; ++s)
             if (!(mm.tau[s] > 0.5) || !std::isfinite(mm.tau[s]))
@@ -266,6 +274,8 @@ int32_t validate(const lb_config *c)
         if (mm.wall_psi != LB_PSI_MIRROR && mm.wall_psi != LB_PSI_ZERO)
             return fail(LB_EINVAL, "member %d: wall_psi = %d is not LB_PSI_MIRROR or LB_PSI_ZERO", m, mm.wall_psi);
         if (mm.reserved != 0) return fail(LB_EINVAL, "member %d: reserved = %d must be 0", m, mm.reserved);
+        if (mm.reserved2[0] != 0.0 || mm.reserved2[1] != 0.0)
+            return fail(LB_EINVAL, "member %d: reserved2 must be 0", m);
         if (!mm.rhoA0 || !mm.rhoB0) return fail(LB_EINVAL, "member %d: initial densities are NULL", m);
         if (mm.ny <= 2 * c->diag_trim) return fail(LB_EINVAL, "member %d: ny = %d leaves no rows after trimming %d", m, mm.ny, c->diag_trim);
     }
@@ -563,42 +573,31 @@ int32_t choose_tiles(lb_handle *h)
     return upload_members(h);
 }
 
-// Per-member storage scales for the 16-bit modes.
+// Per-member code scales of the 16-bit modes.  A code holds the residual
+// f*_i - w_i rho of a site's own density rho: the velocity terms of Eq. 3 and
+// the non-equilibrium part.  At |u| <= 1/2, |c_i . u| <= 0.71, so
+// |f^eq_i - w_i rho| <= w_i rho (3 * 0.71 + 4.5 * 0.5 + 1.5 * 0.25) < 5 w_i rho;
+// with a factor 8 instead of 5, and rho_ref twice the largest initial density
+// of either component (compression, components that spread), the binary16
+// code q = residual * S_i stays below 2^14, far from the format's 65504.
+// bfloat16 has the FP32 exponent range and needs no scale (S_i = 1).
 void set_scales(const lb_config *c, const lb_member &mm, Member &M)
 {
     const int64_t n = (int64_t)mm.nx * mm.ny;
+    double hi = 0.0;
     for (int s = 0; s < 2; ++s) {
         const double *rho = s == 0 ? mm.rhoA0 : mm.rhoB0;
-        double ref = mm.rho0[s];
-        double lo = rho[0], hi = rho[0], sum = 0;
-        for (int64_t k = 0; k < n; ++k) {
-            lo = std::min(lo, rho[k]);
-            hi = std::max(hi, rho[k]);
-            sum += rho[k];
-        }
-        if (ref == 0.0) ref = sum / (double)n;   // default: mean initial density
-        if (ref < 0.0) ref = 0.0;                 // negative: no shift
-        for (int i = 0; i < NQ; ++i) {
-            M.shift[s][i] = 0.0f;
-            M.scale[s][i] = 1.0f;
-            M.iscale[s][i] = 1.0f;
-            if (c->storage == LB_F16S || c->storage == LB_BF16S) {
-                const double w = wgt(i);
-                M.shift[s][i] = (float)(w * ref);
-                // largest excursion |f_i - w_i rho0| expected: the density
-                // spread plus headroom for flow (factor 2).  binary16 keeps
-                // q below 2^14 to stay far from its 65504 limit; bfloat16
-                // has the FP32 exponent range and needs no scale.
-                double span = 2.0 * w * std::max(std::fabs(hi - ref), std::fabs(ref - lo)) + 1e-30;
-                int e = 0;
-                if (c->storage == LB_F16S) e = (int)std::floor(std::log2(16384.0 / span));
-                e = std::max(-60, std::min(60, e));
-                M.scale[s][i] = std::ldexp(1.0f, e);
-                M.iscale[s][i] = std::ldexp(1.0f, -e);
-            }
-            M.nss[s][i] = -M.shift[s][i] * M.scale[s][i];
-        }
+        for (int64_t k = 0; k < n; ++k) hi = std::max(hi, std::fabs(rho[k]));
     }
+    const double rho_ref = 2.0 * std::max(hi, 1e-6);
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < NQ; ++i) {
+            int e = 0;
+            if (c->storage == LB_F16S) e = (int)std::floor(std::log2(16384.0 / (8.0 * wgt(i) * rho_ref)));
+            e = std::max(-60, std::min(60, e));
+            M.scale[s][i] = std::ldexp(1.0f, e);
+            M.iscale[s][i] = std::ldexp(1.0f, -e);
+        }
 }
 
 // Field pass of member m (rho_A, rho_B, u_x, u_y of f(t) into device
@@ -710,10 +709,14 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
         M.nx = mm.nx;
         M.ny = mm.ny;
         M.pitch = (int32_t)pitch_of(mm.nx);
-// row blocks [y][s][i][x]: the 18 row segments of one lattice row are adjacent
+        // row blocks [y][s][i][x]: the 18 row segments of one lattice row are
+        // adjacent; in the 16-bit modes the two FP32 site-density segments
+        // [s][x] follow them
         M.istride = M.pitch;
         M.sstride = (int64_t)NQ * M.pitch;
-        M.ystride = (int64_t)2 * NQ * M.pitch;
+        M.ystride = row_bytes_of(cfg->storage, M.pitch) / (int64_t)elem_bytes(cfg->storage);
+        M.rho_off = site_shift(cfg->storage) ? (int32_t)(2 * NQ * M.pitch * (int64_t)elem_bytes(cfg->storage)) : 0;
+        M.rho_sstride = site_shift(cfg->storage) ? 4 * M.pitch : 0;
         M.f[0] = h->ws + L.fbuf[0][m];
         M.f[1] = h->ws + L.fbuf[1][m];
         for (int s = 0; s < 2; ++s) {
@@ -1015,14 +1018,15 @@ int32_t lb_steps_per_pass(const lb_handle *h)
     return h->steps_per_pass;
 }
 
-int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *shift)
+int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *weight)
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
+    const bool site = site_shift(h->cfg.storage);
     for (int s = 0; s < 2; ++s)
         for (int i = 0; i < NQ; ++i) {
             if (scale) scale[s * NQ + i] = h->dm[m].scale[s][i];
-            if (shift) shift[s * NQ + i] = h->dm[m].shift[s][i];
+            if (weight) weight[s * NQ + i] = site ? (double)(float)wgt(i) : 0.0;
         }
     return LB_OK;
 }

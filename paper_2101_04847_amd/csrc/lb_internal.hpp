@@ -32,10 +32,10 @@ struct alignas(256) Member {
                              //   and row ny - 1 ([s][1]); its x part is exactly 0
     int32_t wall_force;      // 1: aw applies (walls and some G_sb != 0)
     int32_t psi_zero;        // 1: psi = 0 on boundary nodes in Eq. 5; 0: psi of the wall row
-    float shift[2][NQ];      // 16-bit modes: w_i rho0_s; else 0
-    float scale[2][NQ];      // 16-bit modes: power-of-two scale; else 1
-    float iscale[2][NQ];     // 1 / scale
-    float nss[2][NQ];        // -shift * scale (exact: scale is a power of two)
+    int32_t rho_off;         // 16-bit modes: byte offset of the site densities in a row block
+    int32_t rho_sstride;     //   and bytes between the two components' density segments
+    float scale[2][NQ];      // 16-bit modes: power-of-two scale of the codes; else 1
+    float iscale[2][NQ];     // 1 / scale (exact)
 };
 
 // Storage modes (values equal the LB_F64 .. LB_BF16S constants of lb.h).

@@ -70,6 +70,7 @@ struct RowPull {
     rsrc_t r0, rm, rp;
     unsigned oc, om, op;    // source columns c, c - 1 (c_x = +1), c + 1 (c_x = -1)
     unsigned is, ss;        // bytes between populations, between components
+    int cc, cm, cp;         // the three source columns
     bool bb_lo, bb_hi;      // row y - 1 / y + 1 lies beyond a wall
 
     __device__ __forceinline__ RowPull(const void *src, const Member &M, int y, int c)
@@ -78,9 +79,12 @@ struct RowPull {
         const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
         is = (unsigned)M.istride * (unsigned)sizeof(T);
         ss = (unsigned)M.sstride * (unsigned)sizeof(T);
-        oc = (unsigned)c * (unsigned)sizeof(T);
-        om = (unsigned)((c == 0) ? nx - 1 : c - 1) * (unsigned)sizeof(T);
-        op = (unsigned)((c == nx - 1) ? 0 : c + 1) * (unsigned)sizeof(T);
+        cc = c;
+        cm = (c == 0) ? nx - 1 : c - 1;
+        cp = (c == nx - 1) ? 0 : c + 1;
+        oc = (unsigned)cc * (unsigned)sizeof(T);
+        om = (unsigned)cm * (unsigned)sizeof(T);
+        op = (unsigned)cp * (unsigned)sizeof(T);
         int ym = y - 1, yp = y + 1;   // source rows for c_y = +1 / -1
         bb_lo = bb_hi = false;
         if (BCY == BC_PERIODIC) {
@@ -115,7 +119,55 @@ struct RowPull {
             default: return bload<T>(rp, bb_hi ? oc : om, b + (bb_hi ? 6 : 8) * is);
         }
     }
+
+    // 16-bit modes: the stored density of component s at the site that
+    // population i is pulled from (the same site as load(s, i)).
+    __device__ __forceinline__ float load_rho(const Member &M, int s, int i) const
+    {
+        const unsigned b = (unsigned)M.rho_off + (unsigned)s * (unsigned)M.rho_sstride;
+        const unsigned fc = (unsigned)cc * 4u, fm = (unsigned)cm * 4u, fp = (unsigned)cp * 4u;
+        switch (i) {
+            case 0: return bload<float>(r0, fc, b);
+            case 1: return bload<float>(r0, fm, b);
+            case 3: return bload<float>(r0, fp, b);
+            case 2: return bload<float>(rm, fc, b);
+            case 5: return bload<float>(rm, bb_lo ? fc : fm, b);
+            case 6: return bload<float>(rm, bb_lo ? fc : fp, b);
+            case 4: return bload<float>(rp, fc, b);
+            case 7: return bload<float>(rp, bb_hi ? fc : fp, b);
+            default: return bload<float>(rp, bb_hi ? fc : fm, b);
+        }
+    }
 };
+
+// 16-bit modes: population i decoded from its code q and the stored density
+// rhat of the site it was stored at, f = w_i rhat + q / S_i.
+template <int ST>
+__device__ __forceinline__ float site_decode(typename Tr<ST>::T q, float rhat, int i, float iscale)
+{
+    return fmaf(Tr<ST>::value(q), iscale, (float)wgt(i) * rhat);
+}
+
+// 16-bit modes: codes of the post-collision populations of component s at
+// one site of density rho, q_i = code((post_i - w_i r) S_i) with r = rho
+// rounded to FP32, and the stored density rhat = rho - sum_i q_i / S_i: the
+// decoded populations w_i rhat + q_i / S_i then sum to rho up to FP32
+// rounding (sum_i w_i = 1), whatever the rounding of the codes, so the codes
+// carry no systematic mass error.
+template <int ST>
+__device__ __forceinline__ void site_encode(const Member &M, int s, double rho, const float (&post)[NQ],
+                                            typename Tr<ST>::T (&q)[NQ], float &rhat)
+{
+    const float r = (float)rho;
+    float e = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const float d = fmaf(-(float)wgt(i), r, post[i]);
+        q[i] = Tr<ST>::code(d * M.scale[s][i]);
+        e += Tr<ST>::value(q[i]) * M.iscale[s][i];
+    }
+    rhat = (float)(rho - (double)e);
+}
 
 // Pull the 18 pre-collision populations f(t) of column c, row y from the
 // post-collision buffer src, the loads grouped by source row.
@@ -131,8 +183,43 @@ __device__ __forceinline__ void pull_site(const void *src, const Member &M, int 
         typename Q::T v[NQ];
 #pragma unroll
         for (int j = 0; j < NQ; ++j) v[ORDER[j]] = pr.load(s, ORDER[j]);
+        if constexpr (Q::SITE) {
+            float rh[NQ];
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) f[s][i] = Q::dec(v[i], M.shift[s][i], M.iscale[s][i]);
+            for (int j = 0; j < NQ; ++j) rh[ORDER[j]] = pr.load_rho(M, s, ORDER[j]);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) f[s][i] = site_decode<ST>(v[i], rh[i], i, M.iscale[s][i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) f[s][i] = Q::dec(v[i]);
+        }
+    }
+}
+
+// Store the post-collision populations of one site (column byte offset ox
+// of row resource wr) in the storage mode; post[s][i] in the arithmetic type.
+// x is the site's column (for the 16-bit modes' density segment).
+template <int ST>
+__device__ __forceinline__ void store_site(const Member &M, rsrc_t wr, unsigned ox, int x, unsigned wis, unsigned wss,
+                                           const double (&rho)[2], const typename Tr<ST>::C (&post)[2][NQ])
+{
+    using Q = Tr<ST>;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        if constexpr (Q::SITE) {
+            typename Q::T q[NQ];
+            float rhat;
+            site_encode<ST>(M, s, rho[s], post[s], q, rhat);
+#pragma unroll
+            for (int i = 0; i < NQ; ++i)
+                bstore<LBK_NT_STORE ? CPOL_NT : 0>(q[i], wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+            bstore<LBK_NT_STORE ? CPOL_NT : 0>(rhat, wr, (unsigned)x * 4u,
+                                                (unsigned)M.rho_off + (unsigned)s * (unsigned)M.rho_sstride);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i)
+                bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post[s][i]), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+        }
     }
 }
 
@@ -409,10 +496,15 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
         const unsigned ox = (unsigned)x * (unsigned)sizeof(T);
         const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
         const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
-        collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, wrow, [&](int s, int i, C post) {
-            bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
-                                                (unsigned)s * wss + (unsigned)i * wis);
-        });
+        if constexpr (Q::SITE) {
+            C post[2][NQ];
+            collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, wrow, [&](int s, int i, C p) { post[s][i] = p; });
+            store_site<ST>(M, wr, ox, x, wis, wss, rho_c, post);
+        } else {
+            collide_site<ST, FORCING>(M, cur_f, rho_c, Sx, Sy, wrow, [&](int s, int i, C post) {
+                bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+            });
+        }
     }
 }
 
@@ -864,8 +956,20 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
             if constexpr (DIR > 0) sc_sums_lanes(rb, r1c, rf, Sx, Sy);
             else sc_sums_lanes(rf, r1c, rb, Sx, Sy);
             collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, wall_row<BCY>(M, a), [&](int s, int i, C post) {
-                out1[s][i] = Q::dec(Q::enc(post, M.nss[s][i], M.scale[s][i]), M.shift[s][i], M.iscale[s][i]);
+                if constexpr (Q::SITE) out1[s][i] = post;
+                else out1[s][i] = Q::dec(Q::enc(post));
             });
+            if constexpr (Q::SITE) {
+                // the stored form, decoded as the next step pulls it
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    typename Q::T q[NQ];
+                    float rhat;
+                    site_encode<ST>(M, s, r1c[s], out1[s], q, rhat);
+#pragma unroll
+                    for (int i = 0; i < NQ; ++i) out1[s][i] = site_decode<ST>(q[i], rhat, i, M.iscale[s][i]);
+                }
+            }
         } else if (BCY != BC_PERIODIC) {
             // row a lies beyond a wall: the pull of row a - DIR takes its
             // c_y = -DIR populations from its own reversed ones (bounce-back)
@@ -916,11 +1020,17 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
             if constexpr (DIR > 0) sc_sums_lanes(rb, r2c, rf, Sx, Sy);
             else sc_sums_lanes(rf, r2c, rb, Sx, Sy);
             const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
-            collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q), [&](int s, int i, C post) {
-                if (store_ok)
-                    bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post, M.nss[s][i], M.scale[s][i]), wr, ox,
-                                                        (unsigned)s * wss + (unsigned)i * wis);
-            });
+            if constexpr (Q::SITE) {
+                C post[2][NQ];
+                collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q),
+                                          [&](int s, int i, C p) { post[s][i] = p; });
+                if (store_ok) store_site<ST>(M, wr, ox, c, wis, wss, r2c, post);
+            } else {
+                collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q), [&](int s, int i, C post) {
+                    if (store_ok)
+                        bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+                });
+            }
         }
         if (pull_p) {
 #pragma unroll
@@ -1005,6 +1115,7 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
     LBK_GLOBAL T *dst = gp<T>(M.f[cur]);
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(k / M.nx), x = (int)(k % M.nx);
+        double v[2][NQ];   // the stored (post-collision) values of this site
 #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             int xs = x + cx(i), ys = y + cy(i);
@@ -1022,11 +1133,32 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
             const int64_t ks = (int64_t)ys * M.nx + xs;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                double v;
-                if (from_rho) v = wgt(isrc) * (s == 0 ? rhoA[ks] : rhoB[ks]);
-                else v = fcan[((int64_t)s * NQ + isrc) * n + ks];
-                dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] =
-                    Q::enc((typename Q::C)v, M.nss[s][i], M.scale[s][i]);
+                if (from_rho) v[s][i] = wgt(isrc) * (s == 0 ? rhoA[ks] : rhoB[ks]);
+                else v[s][i] = fcan[((int64_t)s * NQ + isrc) * n + ks];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if constexpr (Q::SITE) {
+                // the site's stored density: the sum of its stored populations
+                double rho = v[s][0];
+#pragma unroll
+                for (int i = 1; i < NQ; ++i) rho += v[s][i];
+                float post[NQ];
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) post[i] = (float)v[s][i];
+                T q[NQ];
+                float rhat;
+                site_encode<ST>(M, s, rho, post, q, rhat);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] = q[i];
+                LBK_GLOBAL char *row = (LBK_GLOBAL char *)dst + (int64_t)y * M.ystride * (int64_t)sizeof(T);
+                *(LBK_GLOBAL float *)(row + M.rho_off + (int64_t)s * M.rho_sstride + 4 * (int64_t)x) = rhat;
+            } else {
+#pragma unroll
+                for (int i = 0; i < NQ; ++i)
+                    dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] =
+                        Q::enc((typename Q::C)v[s][i]);
             }
         }
     }

@@ -103,46 +103,54 @@ __device__ __forceinline__ void bstore(uint16_t v, rsrc_t r, unsigned voff, unsi
 }
 
 // ---------------------------------------------------------------------------
-// Storage traits: element type T in memory, arithmetic type C of the collision.
+// Storage traits: element type T in memory, arithmetic type C of the
+// collision, and SITE: whether the codes are shifted by each site's own
+// density (the 16-bit modes, see below).
 template <int ST> struct Tr;
 
 template <> struct Tr<ST_F64> {
     using T = double;
     using C = double;
-    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
-    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
+    static constexpr bool SITE = false;
+    static __device__ __forceinline__ C dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(C v) { return v; }
 };
 
 template <> struct Tr<ST_F32> {
     using T = float;
     using C = float;
-    static __device__ __forceinline__ C dec(T v, float, float) { return v; }
-    static __device__ __forceinline__ T enc(C v, float, float) { return v; }
+    static constexpr bool SITE = false;
+    static __device__ __forceinline__ C dec(T v) { return v; }
+    static __device__ __forceinline__ T enc(C v) { return v; }
 };
 
-// IEEE binary16 holding q = (f - shift) * scale; f = shift + q / scale.  The
-// scales are powers of two, so q * (1/scale) and f * scale are exact and the
-// fused forms below round exactly like the two-operation definitions
-// (nss = -shift * scale).
+// The 16-bit modes store, per site x and component s, the FP32 density
+// rhat_s(x) and for every population a code q_i = (f*_i - w_i r) S_i rounded
+// to the 16-bit format (r: the site density rounded to FP32, S_i a power of
+// two); a population decodes as f*_i = w_i rhat + q_i / S_i.  rhat is chosen
+// so that the decoded populations of a site sum to its density (see
+// site_encode in lb_kernels.hpp).  code() rounds a scaled residual to the
+// format, value() returns the code as FP32 (exact).
+
+// IEEE binary16 codes.
 template <> struct Tr<ST_F16S> {
     using T = _Float16;
     using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf((float)v, iscale, shift); }
-    static __device__ __forceinline__ T enc(C v, float nss, float scale) { return (_Float16)fmaf(v, scale, nss); }
+    static constexpr bool SITE = true;
+    static __device__ __forceinline__ T code(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ float value(T v) { return (float)v; }
 };
 
-// bfloat16 (kept as raw 16-bit patterns) holding the same shifted, scaled q;
-// the conversion rounds to nearest even (gfx950 converts in hardware).
+// bfloat16 codes (kept as raw 16-bit patterns); the conversion rounds to
+// nearest even (gfx950 converts in hardware).
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 template <> struct Tr<ST_BF16S> {
     using T = uint16_t;
     using C = float;
-    static __device__ __forceinline__ C dec(T v, float shift, float iscale) { return fmaf(bf16_to_f32(v), iscale, shift); }
-    static __device__ __forceinline__ T enc(C v, float nss, float scale)
-    {
-        return __builtin_bit_cast(uint16_t, (__bf16)fmaf(v, scale, nss));
-    }
+    static constexpr bool SITE = true;
+    static __device__ __forceinline__ T code(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+    static __device__ __forceinline__ float value(T v) { return bf16_to_f32(v); }
 };
 
 }  // namespace lbk

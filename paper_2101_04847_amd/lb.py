@@ -39,7 +39,7 @@ class LbMember(ctypes.Structure):
                 ("tau", ctypes.c_double * 2), ("G_AB", ctypes.c_double),
                 ("g", (ctypes.c_double * 2) * 2),
                 ("rhoA0", _dp), ("rhoB0", _dp),
-                ("rho0", ctypes.c_double * 2),
+                ("reserved2", ctypes.c_double * 2),
                 ("G_wall", ctypes.c_double * 2), ("wall_psi", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
@@ -150,7 +150,6 @@ class Member:
     tau: tuple = (1.0, 1.0)
     G: float = 0.0
     g: tuple = ((0.0, 0.0), (0.0, 0.0))
-    rho0: tuple = (0.0, 0.0)
     G_wall: tuple = (0.0, 0.0)
     wall_psi: int = 0
 
@@ -171,7 +170,7 @@ def _member_struct(m: Member, keep: list) -> LbMember:
             s.g[c][d] = float(m.g[c][d])
     s.rhoA0 = a.ctypes.data_as(_dp)
     s.rhoB0 = b.ctypes.data_as(_dp)
-    s.rho0[0], s.rho0[1] = float(m.rho0[0]), float(m.rho0[1])
+    s.reserved2[0] = s.reserved2[1] = 0.0
     s.G_wall[0], s.G_wall[1] = float(m.G_wall[0]), float(m.G_wall[1])
     s.wall_psi = int(m.wall_psi)
     s.reserved = 0
@@ -253,9 +252,11 @@ class Lattice:
         return n
 
     def storage_scale(self, m: int = 0):
-        sc, sh = (ctypes.c_double * 18)(), (ctypes.c_double * 18)()
-        _check(_lib.lb_storage_scale(self._h, m, sc, sh), "lb_storage_scale")
-        return np.array(sc[:]).reshape(2, 9), np.array(sh[:]).reshape(2, 9)
+        """(scale, weight), each [2][9]: the code scales of the 16-bit modes and
+        the factors w_i of the per-site shift (1 and 0 in the other modes)."""
+        sc, w = (ctypes.c_double * 18)(), (ctypes.c_double * 18)()
+        _check(_lib.lb_storage_scale(self._h, m, sc, w), "lb_storage_scale")
+        return np.array(sc[:]).reshape(2, 9), np.array(w[:]).reshape(2, 9)
 
     def step(self, n: int = 1) -> None:
         _check(_lib.lb_step(self._h, int(n)), "lb_step")

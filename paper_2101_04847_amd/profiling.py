@@ -85,7 +85,7 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, regex, copy_by
     kw = copy_bytes / (cw_kib * 1024.0)
     read = f_kib * 1024.0 * kf
     write = w_kib * 1024.0 * kw
-    bpl = {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}[storage]
+    bpl = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}[storage]
     alg = bpl * nx * ny
     return {"storage": storage, "nx": nx, "ny": ny, "source_hash": kernel_source_hash(),
             "bytes_per_launch": round(read + write), "read_bytes": round(read), "write_bytes": round(write),

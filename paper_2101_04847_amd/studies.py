@@ -34,11 +34,11 @@ import numpy as np
 TRIM = 10
 
 
-def _lattice(lb, wls, storage, stream, rho0=(0.0, 0.0)):
+def _lattice(lb, wls, storage, stream):
     members = []
     for wl in wls:
         rA, rB = wl.densities()
-        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity, rho0=rho0))
+        members.append(lb.Member(wl.nx, wl.ny, rA, rB, tau=(wl.tau, wl.tau), G=wl.G, g=wl.gravity))
     return lb.Lattice(members, forcing=lb.FORCE_SHIFT, storage=storage, graph_chunk=100, stream=stream,
                       diag_trim=TRIM)
 
@@ -85,8 +85,8 @@ def fp32_vs_fp64_large(lb, inputs, stream, log, steps=2000):
 BUDGET_KEYS = ("pb", "korteweg", "ktau", "viscous")
 
 
-def _series(lb, wls, storage, stream, steps, every, log, tag, rho0=(0.0, 0.0), budget=False):
-    lat = _lattice(lb, wls, storage, stream, rho0)
+def _series(lb, wls, storage, stream, steps, every, log, tag, budget=False):
+    lat = _lattice(lb, wls, storage, stream)
     n = len(wls)
     keys = ["t", "mass_A", "mass_B", "Ek", "Ep", "buoyancy", "omega2", "h"]
     if budget:
@@ -128,12 +128,8 @@ def reduced_precision(lb, inputs, stream, log, steps=20000, every=100):
         ref_series, ref_final = _series(lb, [wl], lb.F64, stream, steps, every, log, f"{wl.name} f64")
         r = ref_series[0]
         h64 = np.array(r["h"])
-        # 16-bit codes shifted by w_i times the mean density (the default), and
-        # unshifted ("-noshift"): floats keep relative precision, so the shift
-        # helps the majority phase of a component and hurts its trace phase
-        for name, st, r0 in (("f32", lb.F32, 0.0), ("f16s", lb.F16S, 0.0), ("bf16s", lb.BF16S, 0.0),
-                             ("f16s-noshift", lb.F16S, -1.0), ("bf16s-noshift", lb.BF16S, -1.0)):
-            ser, fin = _series(lb, [wl], st, stream, steps, every, log, f"{wl.name} {name}", (r0, r0))
+        for name, st in (("f32", lb.F32), ("f16s", lb.F16S), ("bf16s", lb.BF16S)):
+            ser, fin = _series(lb, [wl], st, stream, steps, every, log, f"{wl.name} {name}")
             s = ser[0]
             mA, mB = np.array(s["mass_A"]), np.array(s["mass_B"])
             h = np.array(s["h"])

@@ -65,7 +65,8 @@ def test_workspace_bytes_accounts_for_storage(lb):
     pitch = 128
     pops = 2 * 9 * 40 * pitch
     assert b64 - b32 == 2 * pops * 4
-    assert b32 - b16 == 2 * pops * 2
+    # the 16-bit modes add two FP32 site-density segments per row block
+    assert b32 - b16 == 2 * pops * 2 - 2 * (2 * 40 * pitch * 4)
     assert b64 >= 2 * pops * 8 + 4 * 100 * 40 * 8
 
 

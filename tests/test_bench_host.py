@@ -20,8 +20,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_per_update():
-    # 2 components x 9 populations x (read + write) x element size
-    assert bench.BYTES_PER_LU == {"f64": 288, "f32": 144, "f16s": 72, "bf16s": 72}
+    # 2 components x 9 populations x (read + write) x element size, plus the
+    # two FP32 site densities of the 16-bit modes
+    assert bench.BYTES_PER_LU == {"f64": 288, "f32": 144, "f16s": 2 * (18 * 2 + 2 * 4), "bf16s": 88}
     # 3D: 2 x 19 populations read and written once (fused), plus a second
     # read and the density buffer in the two-pass step
     assert bench.BYTES_PER_LU_3D_FUSED == {"f64": 608, "f32": 304}

@@ -169,8 +169,9 @@ def test_3d_medium_lattice(lb3):
 @pytest.mark.timeout(900)
 def test_3d_bench_size_two_steps(lb3):
     """The benchmark's 3D lattice (384^3, 8 random interface modes, walls,
-    tau = 1, G = 1.5, g = 1e-5): two steps, every density and velocity
-    against the oracle; the FP32 lattice's densities within 1e-6."""
+    tau = 1, G = 1.5, g = 1e-5): two steps of the fused and of the two-pass
+    step (equal bit for bit), every density and velocity against the oracle;
+    the FP32 lattice's densities within 1e-6."""
     import torch
     from paper_2101_04847_amd import inputs
     w = inputs.D3_384
@@ -184,6 +185,16 @@ def test_3d_bench_size_two_steps(lb3):
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    # the two-pass step of the benchmark's two-pass line on the same lattice
+    _say("3d bench size, two passes")
+    l2 = lb3.Lattice3(nx, ny, nz, rA, rB, tau=(w["tau"], w["tau"]), G=w["G"], g=gg, two_pass=True)
+    l2.step(2)
+    m2 = {k: v.cpu().numpy() for k, v in l2.fields().items()}
+    l2.close()
+    del l2
+    torch.cuda.empty_cache()
+    for k in ("rhoA", "rhoB", "ux", "uy", "uz"):
+        assert np.array_equal(m2[k], mg[k]), k
     # the FP32 lattice of the benchmark's FP32 line: densities within the format's bound
     l32 = lb3.Lattice3(nx, ny, nz, rA, rB, tau=(w["tau"], w["tau"]), G=w["G"], g=gg, storage=lb3.F32)
     l32.step(2)

@@ -50,8 +50,8 @@ def test_mixing_width_matches_oracle(lb, nx, ny, seed, G, g, steps):
         # slope of at most 6 / |hi - lo| in phibar
         bound = (ny - 20) * 6.0 / abs(hi - lo) * 2e-12 + 1e-13 * max(h_orc, 1.0)
         assert abs(r["width"] - h_orc) <= bound, (t, r["width"], h_orc)
-        # explicit references give the same reduction
-        r2 = lat.mixing_width(0, ref=(lo, hi))
+        # the recorded references passed explicitly give the same reduction
+        r2 = lat.mixing_width(0, ref=(r["lo"], r["hi"]))
         assert r2["width"] == r["width"]
         print(f"t = {t}: width gpu {r['width']:.12f} oracle {h_orc:.12f}", flush=True)
     lat.close()
