@@ -167,9 +167,10 @@ size_t lb_workspace_bytes(const lb_config *cfg);
 /* Create a handle.  Copies the member table and the initial densities,
  * lays out d_workspace (caller-owned, >= lb_workspace_bytes(cfg) bytes,
  * 256-byte aligned), writes f(0) = w_i rho_s(0) for every member (Eq. 3 at
- * rest), picks tile shapes (timing candidates if tile_x == 0, which advances
- * no state) and returns the handle in *out at t = 0.  hip_stream is a
- * hipStream_t (NULL = the null stream).  Synchronises the stream once. */
+ * rest), picks tile shapes (from the tile cache, see lb_tiles_cached, or by
+ * timing candidates if tile_x or tile_h is 0, which advances no state) and
+ * returns the handle in *out at t = 0.  hip_stream is a hipStream_t (NULL =
+ * the null stream).  Synchronises the stream once. */
 int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip_stream,
                 lb_handle **out);
 
@@ -284,6 +285,17 @@ int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *t
 
 /* Time steps per kernel pass of lb_step: 1 or 2 (negative: error code). */
 int32_t lb_steps_per_pass(const lb_handle *h);
+
+/* 1 if lb_init took the pass and tile shapes from the persisted tile cache,
+ * 0 if it timed them (or they were given), negative: error code.  The cache
+ * is a JSON file keyed by the device (architecture, compute units), storage,
+ * forcing, boundary variant, the requested steps_per_pass / tile_x / tile_h
+ * and every member's nx, ny: the environment variable LB_TILE_CACHE names
+ * it ("off" or empty: no cache), by default $XDG_CACHE_HOME/liblb/tiles.json
+ * or $HOME/.cache/liblb/tiles.json.  A choice that is timed is recorded
+ * there; a cached choice gives the same results bit for bit (tile shapes
+ * never change results). */
+int32_t lb_tiles_cached(const lb_handle *h);
 
 /* Storage scale of member m for the 16-bit modes: scale[s*9 + i] receives
  * scale_{s,i} and weight[s*9 + i] the factor w_i (rounded to FP32) of the

@@ -20,6 +20,7 @@
 
 #include "lb.h"
 #include "lb_kernels.hpp"
+#include "lb_tune_cache.hpp"
 
 
 using namespace lbk;
@@ -306,6 +307,7 @@ struct lb_handle {
     hipGraph_t graph_src[2] = {nullptr, nullptr};
     int device = 0;
     std::vector<double> bulk_ref;   // per member: phibar at rows diag_trim and ny - diag_trim - 1 at t = 0
+    int tiles_cached = 0;           // 1: the tile choice came from the persisted cache
 };
 
 namespace {
@@ -483,7 +485,7 @@ int32_t time_shape2(lb_handle *h, const std::vector<int> &th, int reps, float &m
 // gets a shape (it serves odd remainders and the field pass); the two-step
 // pass is planned when it may be used, and with steps_per_pass == 0 the
 // faster of the two per step is selected.
-int32_t choose_tiles(lb_handle *h)
+int32_t search_tiles(lb_handle *h)
 {
     const lb_config &c = h->cfg;
     const size_t nm = h->dm.size();
@@ -571,6 +573,82 @@ int32_t choose_tiles(lb_handle *h)
         if (spp == 2 || best2 < best1) h->steps_per_pass = 2;
     }
     return upload_members(h);
+}
+
+// Size classes of the members (distinct nx, ny in order of first
+// appearance) and each member's class.
+void size_classes(const lb_handle *h, std::vector<std::pair<int, int>> &shapes, std::vector<int> &cls)
+{
+    shapes.clear();
+    cls.assign(h->dm.size(), 0);
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        const std::pair<int, int> key{h->dm[m].nx, h->dm[m].ny};
+        auto it = std::find(shapes.begin(), shapes.end(), key);
+        cls[m] = (int)(it - shapes.begin());
+        if (it == shapes.end()) shapes.push_back(key);
+    }
+}
+
+// Key of the tile choice: device, every input of the search and the member sizes.
+std::string tune_key(const lb_handle *h)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    const lb_config &c = h->cfg;
+    std::string k = arch + "|cu" + std::to_string(cus) + "|st" + std::to_string(c.storage) + "|f" +
+                    std::to_string(c.forcing) + "|bc" + std::to_string(h->kbc) + "|spp" +
+                    std::to_string(c.steps_per_pass) + "|tx" + std::to_string(c.tile_x) + "|th" +
+                    std::to_string(c.tile_h) + "|";
+    for (size_t m = 0; m < h->dm.size(); ++m)
+        k += (m ? "," : "") + std::to_string(h->dm[m].nx) + "x" + std::to_string(h->dm[m].ny);
+    for (char &ch : k)
+        if (ch == '"' || ch == '\\') ch = '_';
+    return k;
+}
+
+// Tile choice: from the persisted cache when it holds this configuration,
+// else by the timed search (whose result is then recorded).  Explicit tile
+// shapes need no search and bypass the cache.
+int32_t choose_tiles(lb_handle *h)
+{
+    const lb_config &c = h->cfg;
+    h->tiles_cached = 0;
+    if (c.tile_x != 0 && c.tile_h != 0) return search_tiles(h);
+    std::vector<std::pair<int, int>> shapes;
+    std::vector<int> cls;
+    size_classes(h, shapes, cls);
+    const std::string key = tune_key(h);
+    lbtune::Choice ch;
+    if (lbtune::lookup(key, ch) && (ch.spp == 1 || ch.spp == 2) && tx_index(ch.tx) >= 0 &&
+        ch.th.size() == shapes.size() && ch.th2.size() == shapes.size()) {
+        std::vector<int> th(h->dm.size()), th2(h->dm.size());
+        for (size_t m = 0; m < h->dm.size(); ++m) {
+            th[m] = std::max(1, ch.th[cls[m]]);
+            th2[m] = std::max(1, ch.th2[cls[m]]);
+        }
+        plan_tiles(h, ch.tx, th);
+        plan_tiles2(h, th2);
+        h->steps_per_pass = ch.spp;
+        h->tiles_cached = 1;
+        return upload_members(h);
+    }
+    int32_t rc = search_tiles(h);
+    if (rc) return rc;
+    ch.spp = h->steps_per_pass;
+    ch.tx = h->tile_x;
+    ch.th.assign(shapes.size(), 0);
+    ch.th2.assign(shapes.size(), 0);
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        ch.th[cls[m]] = h->dm[m].tile_h;
+        ch.th2[cls[m]] = h->dm[m].tile_h2;
+    }
+    lbtune::store(key, ch);
+    return LB_OK;
 }
 
 // Per-member code scales of the 16-bit modes.  A code holds the residual
@@ -1016,6 +1094,12 @@ int32_t lb_steps_per_pass(const lb_handle *h)
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     return h->steps_per_pass;
+}
+
+int32_t lb_tiles_cached(const lb_handle *h)
+{
+    if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
+    return h->tiles_cached;
 }
 
 int32_t lb_storage_scale(const lb_handle *h, int32_t m, double *scale, double *weight)

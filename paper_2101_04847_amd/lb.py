@@ -107,6 +107,8 @@ _lib.lb_tile_shape.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32
 _lib.lb_tile_shape.restype = ctypes.c_int32
 _lib.lb_steps_per_pass.argtypes = [_h]
 _lib.lb_steps_per_pass.restype = ctypes.c_int32
+_lib.lb_tiles_cached.argtypes = [_h]
+_lib.lb_tiles_cached.restype = ctypes.c_int32
 _lib.lb_storage_scale.argtypes = [_h, ctypes.c_int32, _dp, _dp]
 _lib.lb_storage_scale.restype = ctypes.c_int32
 _lib.lb_destroy.argtypes = [_h]
@@ -118,7 +120,7 @@ EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnost
            "lb_energy_budget",
            "lb_interface_length", "lb_components",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
-           "lb_steps_per_pass", "lb_storage_scale", "lb_destroy", "lb_last_error")
+           "lb_steps_per_pass", "lb_tiles_cached", "lb_storage_scale", "lb_destroy", "lb_last_error")
 
 
 class LBError(RuntimeError):
@@ -250,6 +252,14 @@ class Lattice:
         if n < 0:
             raise LBError(n, "lb_steps_per_pass")
         return n
+
+    @property
+    def tiles_cached(self) -> bool:
+        """True if lb_init took the tile shapes from the persisted cache."""
+        n = int(_lib.lb_tiles_cached(self._h))
+        if n < 0:
+            raise LBError(n, "lb_tiles_cached")
+        return bool(n)
 
     def storage_scale(self, m: int = 0):
         """(scale, weight), each [2][9]: the code scales of the 16-bit modes and

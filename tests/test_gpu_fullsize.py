@@ -94,11 +94,15 @@ def test_production_size():
         states.append(f.copy())
     m3 = oracle.macro(p, f)
     scale = max(np.max(np.abs(m3["rhoA"])), np.max(np.abs(m3["rhoB"])))
+    # errors measured on the MI355X (deterministic for a build); the bar is
+    # four times these, inside the rounding bound (ratios 8 to 12)
+    measured = {"f32": 1.39e-7, "f16s": 4.22e-5, "bf16s": 3.75e-4}
     for name in ("f32", "f16s", "bf16s"):
         b = _bound(states, rows, name, scale)
         err = max(np.max(np.abs(reduced[name][k] - m3[k])) for k in ("rhoA", "rhoB")) / scale
         print(f"[case] {name} density max rel err {err:.3e}, rounding bound {b:.3e} (ratio {b / err:.1f})", flush=True)
         assert err <= b, (name, err, b)
+        assert err <= 4.0 * measured[name], (name, err)
     del states
     oracle.run_inplace(p, f, 8)
     mo = oracle.macro(p, f)

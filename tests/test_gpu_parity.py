@@ -359,11 +359,22 @@ def _storage_error_bound(p, f, steps, storage):
     return out
 
 
+# Density errors of the reduced-precision modes measured on the MI355X for
+# this lattice after 1, 10 and 100 steps.  The arithmetic is deterministic
+# and independent of the tile shape, so the same build reproduces them; the
+# test bar is four times these, well inside the rounding bound (which the
+# errors meet with ratios of 7 to 80), so that a bias in the reduced-precision
+# collision (a wrong coefficient, a lost rounding step) fails the test.
+MEASURED_128x64 = {"f32": (8.49e-8, 2.15e-7, 1.46e-6), "f16s": (2.53e-5, 2.40e-5, 1.32e-4),
+                   "bf16s": (2.00e-4, 2.95e-4, 7.75e-4)}
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16s", "bf16s"])
 def test_reduced_precision_close_to_oracle(lb, storage):
     """Reduced-precision storage follows the FP64 oracle within the bound that
-    the rounding of the stored values implies (_storage_error_bound), after
-    1, 10 and 100 steps; the errors are printed beside their bounds."""
+    the rounding of the stored values implies (_storage_error_bound) and
+    within four times the error measured on the MI355X, after 1, 10 and 100
+    steps; the errors are printed beside their bounds."""
     _say("reduced precision", storage)
     st = {"f32": lb.F32, "f16s": lb.F16S, "bf16s": lb.BF16S}[storage]
     lat, p, f = _pair(lb, 128, 64, storage=st, g=1e-4)
@@ -380,7 +391,8 @@ def test_reduced_precision_close_to_oracle(lb, storage):
         errs.append(max(_rel(mg["rhoA"].cpu().numpy(), mo["rhoA"]), _rel(mg["rhoB"].cpu().numpy(), mo["rhoB"])))
     print(storage, "density rel err after", checkpoints, ":", errs, "bounds", bounds,
           "ratios", [b / max(e, 1e-300) for e, b in zip(errs, bounds)], flush=True)
-    for e, b in zip(errs, bounds):
+    for e, b, m in zip(errs, bounds, MEASURED_128x64[storage]):
         assert e <= b
+        assert e <= 4.0 * m, (e, m)
     assert lat.diagnostics(0)["finite"]
     lat.close()
