@@ -211,6 +211,29 @@ typedef struct lb_mixing {
  * or equal.  Uses the workspace field buffer.  Synchronises the stream. */
 int32_t lb_mixing_width(lb_handle *h, int32_t m, const double *ref, lb_mixing *out);
 
+/* Largest ny accepted by lb_diagnostics_noalloc. */
+#define LB_NOALLOC_MAX_NY 16384
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * averages of lb_diagnostics computed from caller fields, with no handle, no
+ * workspace and no allocation of any kind.  d_rhoA, d_rhoB, d_ux, d_uy are
+ * device [ny][nx] doubles as lb_fields writes them (u the hydrodynamic
+ * velocity); g[4] = {gA_x, gA_y, gB_x, gB_y} are the body accelerations of
+ * Eq. 7 (host); trim as lb_config.diag_trim; hip_stream a hipStream_t (NULL =
+ * the null stream).  *out (host) receives the lb_diag averages with t = 0,
+ * phi_profile (host, ny doubles, or NULL) the row means of phi.
+ * The per-row partial sums live in a fixed scratch area inside the library
+ * (about 1.3 MB per GPU, held until the process ends): ny above
+ * LB_NOALLOC_MAX_NY returns LB_EINVAL.  All calls on one GPU share that
+ * area, so calls that overlap on one GPU (other host threads, other
+ * streams) race; calls in sequence on one stream do not.  Synchronises the
+ * stream.  Returns LB_ENONFINITE (after filling *out) if a value is not
+ * finite. */
+int32_t lb_diagnostics_noalloc(const double *d_rhoA, const double *d_rhoB, const double *d_ux, const double *d_uy,
+                               int32_t nx, int32_t ny, int32_t trim, const double *g, void *hip_stream,
+                               lb_diag *out, double *phi_profile);
+
 /* Terms of the kinetic-energy balance (Sec. 3, Eq. 17) of member m at time t,
  * averaged like lb_diag over the trimmed domain D, from the fields of
  * lb_fields by centred differences (d_x q = (q(x+1) - q(x-1))/2, x periodic;

@@ -705,8 +705,9 @@ int32_t enqueue_reductions(lb_handle *h, int32_t m)
     if (rc) return rc;
     double *part = (double *)(h->ws + h->L.part);
     double *red = (double *)(h->ws + h->L.red);
-    hipLaunchKernelGGL(k_reduce_rows, dim3(M.ny), dim3(RED_THREADS), 0, h->stream, (const double *)fld, M.nx, M.ny,
-                       h->cfg.diag_trim, mm.g[0][0], mm.g[0][1], mm.g[1][0], mm.g[1][1], part);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(M.ny), dim3(RED_THREADS), 0, h->stream, (const double *)fld,
+                       (const double *)(fld + n), (const double *)(fld + 2 * n), (const double *)(fld + 3 * n), M.nx,
+                       M.ny, h->cfg.diag_trim, mm.g[0][0], mm.g[0][1], mm.g[1][0], mm.g[1][1], part);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, h->stream, (const double *)part, M.nx, M.ny, red,
                        red + RED_NQ);
     HIP_TRY(hipGetLastError());
@@ -1127,6 +1128,90 @@ int32_t lb_destroy(lb_handle *h)
     if (h->capture) (void)hipStreamDestroy(h->capture);
     delete h;
     if (e != hipSuccess) return fail(LB_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// lb_diagnostics_noalloc: the reductions of lb_diagnostics over caller fields,
+// with the per-row partial sums and the results in a file-scope device array
+// instead of a workspace.  Every GPU the library runs on holds one copy of
+// the array until the process ends; calls on one GPU share it.
+
+}  // extern "C"
+
+namespace {
+
+constexpr int64_t NOALLOC_PART = (int64_t)LB_NOALLOC_MAX_NY * RED_NQ;   // [ny][RED_NQ] row partials
+constexpr int64_t NOALLOC_DOUBLES = NOALLOC_PART + RED_NQ + LB_NOALLOC_MAX_NY;   // + totals + row profile
+
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device; the array's name is only a host-side stand-in).
+int32_t scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(LB_EINVAL, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        double *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LB_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lb_diagnostics_noalloc(const double *d_rhoA, const double *d_rhoB, const double *d_ux, const double *d_uy,
+                               int32_t nx, int32_t ny, int32_t trim, const double *g, void *hip_stream, lb_diag *out,
+                               double *phi_profile)
+{
+    if (!d_rhoA || !d_rhoB || !d_ux || !d_uy) return fail(LB_EINVAL, "a field pointer is NULL");
+    if (!g || !out) return fail(LB_EINVAL, "g or out is NULL");
+    if (nx < 1 || ny < 3) return fail(LB_EINVAL, "nx = %d, ny = %d must be >= 1 and >= 3", nx, ny);
+    if (ny > LB_NOALLOC_MAX_NY)
+        return fail(LB_EINVAL, "ny = %d exceeds LB_NOALLOC_MAX_NY = %d (the fixed scratch holds that many rows)", ny,
+                    LB_NOALLOC_MAX_NY);
+    if (trim < 1 || ny <= 2 * trim) return fail(LB_EINVAL, "trim = %d must be >= 1 and leave rows of ny = %d", trim, ny);
+    double *ptr = nullptr;
+    int32_t rc = scratch_on_current_device(&ptr);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    double *part = ptr, *red = ptr + NOALLOC_PART;
+    // every partial and result read below is written first by these kernels:
+    // nothing needs to start at zero
+    hipLaunchKernelGGL(k_reduce_rows, dim3(ny), dim3(RED_THREADS), 0, s, d_rhoA, d_rhoB, d_ux, d_uy, nx, ny, trim, g[0],
+                       g[1], g[2], g[3], part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, (const double *)part, nx, ny, red,
+                       red + RED_NQ);
+    HIP_TRY(hipGetLastError());
+    double host[RED_NQ];
+    HIP_TRY(hipMemcpyAsync(host, red, sizeof host, hipMemcpyDeviceToHost, s));
+    if (phi_profile)
+        HIP_TRY(hipMemcpyAsync(phi_profile, red + RED_NQ, (size_t)ny * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double nd = (double)nx * (double)(ny - 2 * trim);
+    out->t = 0;
+    out->mass[0] = host[0];
+    out->mass[1] = host[1];
+    out->Ek = host[3] / nd;
+    out->Ep = host[4] / nd;
+    out->buoyancy = host[5] / nd;
+    out->omega2 = host[6] / nd;
+    out->umax = host[7];
+    out->finite = host[8] == 0.0 ? 1 : 0;
+    if (!out->finite) return fail(LB_ENONFINITE, "%.0f non-finite densities or velocities", host[8]);
     return LB_OK;
 }
 

@@ -1228,13 +1228,12 @@ __device__ __forceinline__ double block_combine(double v, double *sh)
 }
 
 __global__ void __launch_bounds__(RED_THREADS)
-k_reduce_rows(const double *__restrict__ fld, int nx, int ny, int trim, double gAx, double gAy, double gBx,
+k_reduce_rows(const double *__restrict__ rA, const double *__restrict__ rB, const double *__restrict__ ux,
+              const double *__restrict__ uy, int nx, int ny, int trim, double gAx, double gAy, double gBx,
               double gBy, double *__restrict__ part)
 {
     __shared__ double sh[RED_THREADS / 64];
     const int y = blockIdx.x;
-    const int64_t n = (int64_t)nx * ny;
-    const double *rA = fld, *rB = fld + n, *ux = fld + 2 * n, *uy = fld + 3 * n;
     const bool inD = (y >= trim) && (y < ny - trim);
     const double yj = (double)y - 0.5 * (double)(ny - 1);
     double a[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};

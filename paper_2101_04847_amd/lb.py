@@ -28,6 +28,7 @@ F64, F32, F16S, BF16S = 0, 1, 2, 3
 WALLS, PERIODIC_Y = 0, 1
 PSI_MIRROR, PSI_ZERO = 0, 1
 MAX_MEMBERS = 64
+NOALLOC_MAX_NY = 16384
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16S: "f16s", BF16S: "bf16s"}
 ELEM_BYTES = {F64: 8, F32: 4, F16S: 2, BF16S: 2}
 
@@ -91,6 +92,9 @@ _lib.lb_diagnostics.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbDiag), _dp]
 _lib.lb_diagnostics.restype = ctypes.c_int32
 _lib.lb_mixing_width.argtypes = [_h, ctypes.c_int32, _dp, ctypes.POINTER(LbMixing)]
 _lib.lb_mixing_width.restype = ctypes.c_int32
+_lib.lb_diagnostics_noalloc.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 3 + [_dp, ctypes.c_void_p,
+                                                                                    ctypes.POINTER(LbDiag), _dp]
+_lib.lb_diagnostics_noalloc.restype = ctypes.c_int32
 _lib.lb_energy_budget.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbBudget)]
 _lib.lb_energy_budget.restype = ctypes.c_int32
 _lib.lb_interface_length.argtypes = [_h, ctypes.c_int32, ctypes.POINTER(LbInterface)]
@@ -116,7 +120,8 @@ _lib.lb_destroy.restype = ctypes.c_int32
 _lib.lb_last_error.argtypes = []
 _lib.lb_last_error.restype = ctypes.c_char_p
 
-EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_mixing_width",
+EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_fields", "lb_diagnostics", "lb_diagnostics_noalloc",
+           "lb_mixing_width",
            "lb_energy_budget",
            "lb_interface_length", "lb_components",
            "lb_get_populations", "lb_set_populations", "lb_time", "lb_tile_shape",
