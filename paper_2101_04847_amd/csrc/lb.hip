@@ -351,7 +351,8 @@ void plan_tiles2(lb_handle *h, const std::vector<int> &th)
         M.tile_h2 = std::max(1, std::min(th[m], M.ny));
         M.tiles_y2 = (M.ny + M.tile_h2 - 1) / M.tile_h2;
         M.item2_begin = item;
-        item += (int64_t)M.tiles_x2 * M.tiles_y2;
+        // whole blocks of NWX windows by NWY bands (k_step2 skips the overhang)
+        item += (int64_t)((M.tiles_x2 + NWX - 1) / NWX) * ((M.tiles_y2 + NWY - 1) / NWY) * NW2;
         M.item2_end = item;
     }
     h->n_items2 = item;
@@ -371,7 +372,8 @@ int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
     if (h->steps_per_pass == 2) {
         Step2Fn fn2 = pick_step2(h->cfg.storage, h->cfg.forcing, h->kbc);
         for (; n >= 2; n -= 2) {
-            hipLaunchKernelGGL(fn2, dim3((unsigned)h->n_items2), dim3(64), 0, s, (const Member *)dev_members(h),
+            hipLaunchKernelGGL(fn2, dim3((unsigned)((h->n_items2 + NW2 - 1) / NW2)), dim3(64 * NW2), 0, s,
+                               (const Member *)dev_members(h),
                                (int)h->dm.size(), (int64_t)0, h->n_items2, cur);
             cur ^= 1;
         }
@@ -461,7 +463,8 @@ int32_t time_shape2(lb_handle *h, const std::vector<int> &th, int reps, float &m
     HIP_TRY(hipEventCreate(&b));
     Step2Fn fn = pick_step2(h->cfg.storage, h->cfg.forcing, h->kbc);
     auto once = [&]() {
-        hipLaunchKernelGGL(fn, dim3((unsigned)h->n_items2), dim3(64), 0, h->stream, (const Member *)dev_members(h),
+        hipLaunchKernelGGL(fn, dim3((unsigned)((h->n_items2 + NW2 - 1) / NW2)), dim3(64 * NW2), 0, h->stream,
+                           (const Member *)dev_members(h),
                            (int)h->dm.size(), (int64_t)0, h->n_items2, h->cur);
     };
     once();  // warm-up

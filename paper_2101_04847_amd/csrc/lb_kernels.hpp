@@ -251,13 +251,34 @@ __device__ __forceinline__ void momentum(const C (&f)[NQ], double &jx, double &j
     jy -= (double)f[8];
 }
 
+// j_s = sum_i f_i^s c_i in the arithmetic type of the reduced-precision
+// collision (FP32), same term order.
+__device__ __forceinline__ void momentum_f(const float (&f)[NQ], float &jx, float &jy)
+{
+    jx = ((f[1] - f[3]) + (f[5] - f[6])) + (f[8] - f[7]);
+    jy = ((f[2] - f[4]) + (f[5] + f[6])) - (f[7] + f[8]);
+}
+
 // ---------------------------------------------------------------------------
 // Eq. 5 neighbour sum S = sum_i w_i psi(x + c_i) c_i of one component, in
 // index order (i = 1..8), from its eight neighbour densities p1..p8 (p_i at
 // x + c_i).
+// FACTORED selects the form w_1 (p1 - p3) + w_5 ((p5 - p7) + (p8 - p6)) (and
+// likewise for y), 12 instead of 22 FP64 operations: the reduced-precision
+// modes use it (in both passes, so they still agree bit for bit); the FP64
+// mode and the field pass keep the index order of the definition.
+template <bool FACTORED = false>
 __device__ __forceinline__ void sc_sum(double p1, double p2, double p3, double p4, double p5, double p6, double p7,
                                        double p8, double &Sx, double &Sy)
 {
+    if constexpr (FACTORED) {
+        const double w1 = wgt(1), w5 = wgt(5);
+        const double d57 = p5 - p7, d86 = p8 - p6;
+        Sx = w1 * (p1 - p3) + w5 * (d57 + d86);
+        Sy = w1 * (p2 - p4) + w5 * (d57 - d86);
+        return;
+    }
+
     const double w1 = wgt(1), w5 = wgt(5);
     double sx = w1 * p1;
     sx -= w1 * p3;
@@ -297,10 +318,10 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
                                              int wrow, Emit &&emit)
 {
     using C = typename Tr<ST>::C;
-    double jx[2], jy[2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s) momentum(cur_f[s], jx[s], jy[s]);
     if constexpr (ST == ST_F64) {
+        double jx[2], jy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) momentum(cur_f[s], jx[s], jy[s]);
         // FP64: the definitions evaluated in their written order.  With
         // psi_s = rho_s, Eq. 5 + Eq. 7 (+ Eq. 6 on a wall row) give
         // F_s = rho_s a_s with the acceleration a_s = -G S_sbar + g_s (+ a^w_s).
@@ -372,9 +393,12 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
             }
         }
     } else {
-        // Reduced-precision modes: the collision in FP32 with fused
-        // multiply-adds.  Densities, the Shan-Chen sums and the
+        // Reduced-precision modes: momenta and the collision in FP32 with
+        // fused multiply-adds.  Densities, the Shan-Chen sums and the
         // accelerations a_s = -G S_sbar + g_s (+ a^w_s) stay FP64.
+        float jx[2], jy[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) momentum_f(cur_f[s], jx[s], jy[s]);
         float rf[2], ax[2], ay[2];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -389,13 +413,13 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
             // Eq. 1: velocity weighted by 1/tau_s
             const float itA = (float)M.itau[0], itB = (float)M.itau[1];
             const float iden = __builtin_amdgcn_rcpf(fmaf(rf[0], itA, rf[1] * itB));
-            ux = fmaf((float)jx[0], itA, (float)jx[1] * itB) * iden;
-            uy = fmaf((float)jy[0], itA, (float)jy[1] * itB) * iden;
+            ux = fmaf(jx[0], itA, jx[1] * itB) * iden;
+            uy = fmaf(jy[0], itA, jy[1] * itB) * iden;
         } else {
             // Guo: (sum_s j_s + F / 2) / rho
             const float irt = __builtin_amdgcn_rcpf(rf[0] + rf[1]);
-            ux = fmaf(0.5f, fmaf(rf[0], ax[0], rf[1] * ax[1]), (float)jx[0] + (float)jx[1]) * irt;
-            uy = fmaf(0.5f, fmaf(rf[0], ay[0], rf[1] * ay[1]), (float)jy[0] + (float)jy[1]) * irt;
+            ux = fmaf(0.5f, fmaf(rf[0], ax[0], rf[1] * ax[1]), jx[0] + jx[1]) * irt;
+            uy = fmaf(0.5f, fmaf(rf[0], ay[0], rf[1] * ay[1]), jy[0] + jy[1]) * irt;
         }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -469,7 +493,7 @@ __device__ __forceinline__ void row_update(const Member &M, const double (&ring)
     double Sx[2], Sy[2];
 #pragma unroll
     for (int o = 0; o < 2; ++o)
-        sc_sum(ring[s0][o][e + 1], ring[sp][o][e], ring[s0][o][e - 1], ring[sm][o][e], ring[sp][o][e + 1],
+        sc_sum<!FIELDS && ST != ST_F64>(ring[s0][o][e + 1], ring[sp][o][e], ring[s0][o][e - 1], ring[sm][o][e], ring[sp][o][e + 1],
                ring[sp][o][e - 1], ring[sm][o][e - 1], ring[sm][o][e + 1], Sx[o], Sy[o]);
     if constexpr (FIELDS) {
         double jx[2], jy[2], Fx[2], Fy[2];
@@ -816,6 +840,41 @@ k_step(const Member *__restrict__ members, int n_members, int64_t item0, int64_t
 // bit.  Populations are read once and written once per two steps; the price
 // is 4 extra step-1 rows per band and 6 extra step-1 columns per 58.
 constexpr int TX2 = 58;                 // output columns per work item
+#ifndef LBK_NW2
+#define LBK_NW2 4
+#endif
+constexpr int NW2 = LBK_NW2;            // waves (work items) per workgroup of the two-step pass
+#ifndef LBK_NWY
+#define LBK_NWY 1
+#endif
+// A workgroup's NW2 items form a block of NWX column windows by NWY bands of
+// one member, so that the waves that share cache lines (neighbouring windows)
+// or halo rows (neighbouring bands, marching towards each other) start
+// together on one CU.
+constexpr int NWY = LBK_NWY;
+constexpr int NWX = NW2 / NWY;
+static_assert(NWX * NWY == NW2, "the workgroup's items form an NWX x NWY block");
+
+// Resident waves per SIMD the two-step pass is held to, per storage mode (0:
+// as many as its registers allow).  The FP64 pass needs 249 VGPRs (two
+// waves); the FP32 pass needs about 150 and would run three waves, which
+// keep more rows in flight per CU than its caches hold (measured 12 %
+// slower at 10000 x 5000); the 16-bit passes are fastest at three.
+template <int ST>
+constexpr int fused_waves_per_simd()
+{
+    return ST == ST_F32 ? 2 : ((ST == ST_F16S || ST == ST_BF16S) ? 3 : 0);
+}
+// LDS a workgroup of the two-step pass reserves (unused) so that no more
+// than fused_waves_per_simd waves per SIMD are resident: one byte more per
+// workgroup than fits one extra workgroup into the 160 KB of a CU.
+constexpr int LDS_PER_CU = 160 * 1024;
+template <int ST>
+constexpr int fused_lds_cap_floats()
+{
+    return fused_waves_per_simd<ST>() == 0 ? 0
+                                           : (LDS_PER_CU / (4 * fused_waves_per_simd<ST>() / NW2 + 1) + 256) / 4;
+}
 constexpr int DPP_WAVE_SHL1 = 0x130;    // lane l receives lane l + 1 (column x + 1)
 constexpr int DPP_WAVE_SHR1 = 0x138;    // lane l receives lane l - 1 (column x - 1)
 
@@ -840,12 +899,13 @@ template <class V> __device__ __forceinline__ V from_right(V v) { return lane_sh
 
 // Eq. 5 sums of both components from the densities of rows y - 1, y, y + 1
 // of this lane's column; the other columns come from the neighbouring lanes.
+template <bool FACTORED>
 __device__ __forceinline__ void sc_sums_lanes(const double (&lo)[2], const double (&mid)[2], const double (&hi)[2],
                                               double (&Sx)[2], double (&Sy)[2])
 {
 #pragma unroll
     for (int o = 0; o < 2; ++o)
-        sc_sum(from_right(mid[o]), hi[o], from_left(mid[o]), lo[o], from_right(hi[o]), from_left(hi[o]),
+        sc_sum<FACTORED>(from_right(mid[o]), hi[o], from_left(mid[o]), lo[o], from_right(hi[o]), from_left(hi[o]),
                from_left(lo[o]), from_right(lo[o]), Sx[o], Sy[o]);
 }
 
@@ -953,8 +1013,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 rf[s] = in_ap ? r1n[s] : (pz ? 0.0 : r1c[s]);
             }
             double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes(rb, r1c, rf, Sx, Sy);
-            else sc_sums_lanes(rf, r1c, rb, Sx, Sy);
+            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64>(rb, r1c, rf, Sx, Sy);
+            else sc_sums_lanes<ST != ST_F64>(rf, r1c, rb, Sx, Sy);
             collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, wall_row<BCY>(M, a), [&](int s, int i, C post) {
                 if constexpr (Q::SITE) out1[s][i] = post;
                 else out1[s][i] = Q::dec(Q::enc(post));
@@ -1017,8 +1077,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 rf[s] = inside(p) ? r2n[s] : (pz ? 0.0 : r2c[s]);
             }
             double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes(rb, r2c, rf, Sx, Sy);
-            else sc_sums_lanes(rf, r2c, rb, Sx, Sy);
+            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64>(rb, r2c, rf, Sx, Sy);
+            else sc_sums_lanes<ST != ST_F64>(rf, r2c, rb, Sx, Sy);
             const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
             if constexpr (Q::SITE) {
                 C post[2][NQ];
@@ -1068,17 +1128,32 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
 // (left alone the compiler takes a few more and drops to one wave); three
 // waves would need spills and measure much slower.
 template <int ST, int FORCING, int BCY>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * NW2) __attribute__((amdgpu_waves_per_eu(2)))
 k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur)
 {
-    const int lane = threadIdx.x;
-    for (int64_t item = item0 + blockIdx.x; item < item0 + n_items; item += gridDim.x) {
+    // NW2 waves per workgroup take NW2 consecutive items: an NWX x NWY block
+    // of column windows and bands of one member
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform across the wave: keep it (and with it the
+    // work item and everything derived from it) in scalar registers
+    const int wave = NW2 == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if constexpr (fused_lds_cap_floats<ST>() > 0) {
+        // reserved to cap the workgroups resident per CU; never read
+        __shared__ float cap[fused_lds_cap_floats<ST>()];
+        if (n_members < 0) cap[threadIdx.x] = 0.0f;
+    }
+    for (int64_t item = item0 + (int64_t)blockIdx.x * NW2 + wave; item < item0 + n_items;
+         item += (int64_t)gridDim.x * NW2) {
         int m = 0;
         while (m + 1 < n_members && members[m].item2_end <= item) ++m;
         const Member &M = members[m];
         const int64_t t = item - M.item2_begin;
-        const int tx = (int)(t % M.tiles_x2);
-        const int ty = (int)(t / M.tiles_x2);
+        const int64_t g = t / NW2;              // block of items, row-major over the member
+        const int w = (int)(t % NW2);
+        const int gxn = (M.tiles_x2 + NWX - 1) / NWX;
+        const int tx = (int)(g % gxn) * NWX + w % NWX;
+        const int ty = (int)(g / gxn) * NWY + w / NWX;
+        if (tx >= M.tiles_x2 || ty >= M.tiles_y2) continue;   // a block's overhang beyond the lattice
         const int x0 = tx * TX2;
         const int y0 = ty * M.tile_h2;
         const int nrows = min(M.tile_h2, M.ny - y0);

@@ -350,10 +350,78 @@ def run_all(lb, inputs, stream, log):
     return rep
 
 
+SUMMARY_KEYS = ("h", "Ek", "Ep", "length", "comp_A", "comp_B", "umax", "viscous", "korteweg", "buoyancy")
+
+
+def _finite_until(series) -> int:
+    """Index of the last sample up to which every quantity of a member is
+    finite (-1 if the first sample is not)."""
+    last = -1
+    for j in range(len(series["t"])):
+        if all(np.isfinite(series[k][j]) for k in SUMMARY_KEYS if k in series):
+            last = j
+        else:
+            break
+    return last
+
+
+def summarise_paper_runs(runs, times=None) -> dict:
+    """Ensemble tables of paper-parameter runs (the output of paper_runs, one
+    or more files per case): per case and sample time, the mean and standard
+    deviation over (a) the members that stay finite to the end of the run
+    and (b) every member still finite at that time (members that fail are
+    included up to their last finite sample), so the effect of dropping the
+    failed members on each statistic is visible; and per member the time of
+    its last finite sample."""
+    by_case = {}
+    for r in runs:
+        c = by_case.setdefault(r["case"], {"G": r["G"], "storage": r["storage"], "members": [], "seeds": []})
+        for k, ser in enumerate(r["members"]):
+            c["members"].append(ser)
+            c["seeds"].append(r["seed0"] + k)
+    out = {}
+    for case, c in by_case.items():
+        mem = c["members"]
+        t_all = mem[0]["t"]
+        sel = times or [t for t in t_all if t and t % 10000 == 0]
+        last = [_finite_until(ser) for ser in mem]
+        end = len(t_all) - 1
+        rows = {}
+        for t in sel:
+            j = t_all.index(t)
+            row = {}
+            for k in SUMMARY_KEYS:
+                if k not in mem[0]:
+                    continue
+                surv = [ser[k][j] for ser, l in zip(mem, last) if l == end]
+                alive = [ser[k][j] for ser, l in zip(mem, last) if l >= j]
+                row[k] = {"survivors": {"mean": float(np.mean(surv)) if surv else None,
+                                        "std": float(np.std(surv)) if surv else None, "n": len(surv)},
+                          "finite_at_t": {"mean": float(np.mean(alive)) if alive else None,
+                                          "std": float(np.std(alive)) if alive else None, "n": len(alive)}}
+            rows[str(t)] = row
+        out[case] = {"G": c["G"], "storage": c["storage"], "members": len(mem),
+                     "finite_to_end": sum(1 for l in last if l == end),
+                     "last_finite_t": {str(s): (t_all[l] if l >= 0 else None) for s, l in zip(c["seeds"], last)},
+                     "tables": rows}
+    return out
+
+
 def main(argv):
-    """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS [STORAGE]]"""
+    """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS [STORAGE]]
+    python -m paper_2101_04847_amd.studies paper-summary OUT.json RUN.json [RUN.json ...]"""
     import json
     import sys as _sys
+
+    if len(argv) >= 3 and argv[0] == "paper-summary":
+        runs = []
+        for path in argv[2:]:
+            with open(path) as fh:
+                runs.append(json.load(fh))
+        with open(argv[1], "w") as fh:
+            json.dump(summarise_paper_runs(runs), fh, indent=1)
+        print(json.dumps({"out": argv[1], "runs": len(runs)}))
+        return
 
     import torch
 
