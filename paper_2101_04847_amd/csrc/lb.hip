@@ -351,8 +351,7 @@ void plan_tiles2(lb_handle *h, const std::vector<int> &th)
         M.tile_h2 = std::max(1, std::min(th[m], M.ny));
         M.tiles_y2 = (M.ny + M.tile_h2 - 1) / M.tile_h2;
         M.item2_begin = item;
-        // whole blocks of NWX windows by NWY bands (k_step2 skips the overhang)
-        item += (int64_t)((M.tiles_x2 + NWX - 1) / NWX) * ((M.tiles_y2 + NWY - 1) / NWY) * NW2;
+        item += (int64_t)M.tiles_x2 * M.tiles_y2;
         M.item2_end = item;
     }
     h->n_items2 = item;

@@ -844,16 +844,6 @@ constexpr int TX2 = 58;                 // output columns per work item
 #define LBK_NW2 4
 #endif
 constexpr int NW2 = LBK_NW2;            // waves (work items) per workgroup of the two-step pass
-#ifndef LBK_NWY
-#define LBK_NWY 1
-#endif
-// A workgroup's NW2 items form a block of NWX column windows by NWY bands of
-// one member, so that the waves that share cache lines (neighbouring windows)
-// or halo rows (neighbouring bands, marching towards each other) start
-// together on one CU.
-constexpr int NWY = LBK_NWY;
-constexpr int NWX = NW2 / NWY;
-static_assert(NWX * NWY == NW2, "the workgroup's items form an NWX x NWY block");
 
 // Resident waves per SIMD the two-step pass is held to, per storage mode (0:
 // as many as its registers allow).  The FP64 pass needs 249 VGPRs (two
@@ -1131,8 +1121,10 @@ template <int ST, int FORCING, int BCY>
 __global__ void __launch_bounds__(64 * NW2) __attribute__((amdgpu_waves_per_eu(2)))
 k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur)
 {
-    // NW2 waves per workgroup take NW2 consecutive items: an NWX x NWY block
-    // of column windows and bands of one member
+    // NW2 waves per workgroup take NW2 consecutive items (neighbouring
+    // column windows of a band, row-major over the members' bands), so that
+    // waves that share cache lines start together on one CU.  Blocks of two
+    // windows by two bands, or four bands, measured slower.
     const int lane = threadIdx.x & 63;
     // the wave index is uniform across the wave: keep it (and with it the
     // work item and everything derived from it) in scalar registers
@@ -1148,12 +1140,8 @@ k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_
         while (m + 1 < n_members && members[m].item2_end <= item) ++m;
         const Member &M = members[m];
         const int64_t t = item - M.item2_begin;
-        const int64_t g = t / NW2;              // block of items, row-major over the member
-        const int w = (int)(t % NW2);
-        const int gxn = (M.tiles_x2 + NWX - 1) / NWX;
-        const int tx = (int)(g % gxn) * NWX + w % NWX;
-        const int ty = (int)(g / gxn) * NWY + w / NWX;
-        if (tx >= M.tiles_x2 || ty >= M.tiles_y2) continue;   // a block's overhang beyond the lattice
+        const int tx = (int)(t % M.tiles_x2);
+        const int ty = (int)(t / M.tiles_x2);
         const int x0 = tx * TX2;
         const int y0 = ty * M.tile_h2;
         const int nrows = min(M.tile_h2, M.ny - y0);
