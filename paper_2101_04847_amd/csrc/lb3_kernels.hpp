@@ -316,9 +316,6 @@ __global__ void __launch_bounds__(WX * WY) k3_collide(Lat3 L, int cur, Fields3 f
 // collision need about 220 VGPRs, so a block of 512 threads (two waves per
 // SIMD) is the largest that fits; taller blocks spill and run slower.
 constexpr int FX = 64, FY = 8;
-#ifndef LB3_XCD_REMAP
-#define LB3_XCD_REMAP 0
-#endif
 
 template <int ST, int BCY>
 __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
@@ -328,19 +325,7 @@ __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
     static_assert(FX == 64, "one wave per thread row: y is uniform across a wave");
     const int lane = threadIdx.x;
     const int ty = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
-#if LB3_XCD_REMAP
-    // consecutive blocks go to different XCDs in turn: give each XCD a
-    // contiguous run of tiles instead (its own L2 then holds shared halos)
-    const int nb = (int)(gridDim.x * gridDim.y * gridDim.z);
-    const int lin = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
-    // XCD r (= lin % 8) takes tiles [r q + min(r, m), ...) with q = nb / 8, m = nb % 8
-    const int r8 = lin % 8, q8 = nb / 8, m8 = nb % 8;
-    const int rl = r8 * q8 + min(r8, m8) + lin / 8;
-    const int bx = rl % (int)gridDim.x, by = (rl / (int)gridDim.x) % (int)gridDim.y,
-              bz = rl / (int)(gridDim.x * gridDim.y);
-#else
     const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-#endif
     const int xu = bx * (FX - 2) - 1 + lane;    // unwrapped column of this thread
     const int yu = by * (FY - 2) - 1 + ty;      // unwrapped row (wave-uniform)
     const int z0 = bz * nzb;
