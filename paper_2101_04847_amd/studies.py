@@ -365,17 +365,98 @@ def _finite_until(series) -> int:
     return last
 
 
+def paper_analysis(members, nx, ny, t_from=10000, t_fit=20000, t_peak_until=50000) -> dict:
+    """Derived statistics of paper-parameter series (members: the series of
+    the members finite to the end of the run; the topology entry also takes
+    failed members up to their last finite sample if they are passed):
+
+    * Eq. 17: over [t_from, end] the change of E_k against the trapezoid
+      integral of -(p_b + Korteweg + K^(tau) fluxes) + viscous - buoyancy;
+      residual relative to the summed magnitudes of the integrated terms
+      (mean and largest over the members) and the member-mean integrals.
+    * Eq. 22: largest relative difference between the viscous term and
+      -eta <omega^2> from t_fit on: the median and largest per-sample
+      relative difference and the range over the members of the ratio of
+      their time integrals.
+    * Topology: per member the first sample at which either phase has more
+      than one connected component.
+    * Interface growth: the rate dL/dt of the member-mean interface length
+      (centred differences), its peak up to t_peak_until and the first local
+      minimum after that peak.
+    * Eq. 21: per member the least-squares slope of <u . div P^K> against
+      (dL/dt) / D (D the averaging area, rows [TRIM, ny - TRIM)) from t_fit
+      on, and the correlation of the two series."""
+    out = {"members": len(members)}
+    need = ("t", "Ek", "pb", "korteweg", "ktau", "viscous", "buoyancy", "eta", "omega2", "length")
+    if not members or any(k not in members[0] for k in need):
+        return out
+    t = np.array(members[0]["t"], dtype=np.float64)
+    j0 = int(np.searchsorted(t, t_from))
+    res, parts = [], []
+    for s in members:
+        rhs = np.stack([-np.array(s["pb"]), -np.array(s["korteweg"]), -np.array(s["ktau"]),
+                        np.array(s["viscous"]), -np.array(s["buoyancy"])], axis=1)
+        integ = np.trapezoid(rhs[j0:], t[j0:], axis=0)
+        d_ek = s["Ek"][-1] - s["Ek"][j0]
+        res.append(float(abs(d_ek - integ.sum()) / np.sum(np.abs(integ))))
+        parts.append(integ)
+    out["eq17_residual_rel"] = {"mean": float(np.mean(res)), "max": float(np.max(res)), "from_t": int(t[j0])}
+    out["eq17_integrals"] = dict(zip(("-pb", "-korteweg", "-ktau", "viscous", "-buoyancy"),
+                                     [float(v) for v in np.mean(np.array(parts), axis=0)]))
+    jf = int(np.searchsorted(t, t_fit))
+    rel, ratio = [], []
+    for s in members:
+        v = np.array(s["viscous"][jf:])
+        e = np.array(s["eta"][jf:]) * np.array(s["omega2"][jf:])
+        rel.append(np.abs(v + e) / np.abs(e))
+        ratio.append(float(np.trapezoid(v, t[jf:]) / np.trapezoid(-e, t[jf:])))
+    out["eq22"] = {"median_rel_diff": float(np.median(np.concatenate(rel))),
+                   "max_rel_diff": float(np.max(np.concatenate(rel))),
+                   "integral_ratio_min": float(np.min(ratio)), "integral_ratio_max": float(np.max(ratio)),
+                   "from_t": int(t[jf])}
+    mean_len = np.mean(np.array([s["length"] for s in members]), axis=0)
+    rate = np.gradient(mean_len, t)
+    sel = np.nonzero(t <= t_peak_until)[0]
+    jp = int(sel[np.argmax(rate[sel])])
+    jm = jp
+    while jm + 1 <= sel[-1] and rate[jm + 1] <= rate[jm]:   # first local minimum after the peak
+        jm += 1
+    out["length_rate"] = {"peak_t": int(t[jp]), "peak": float(rate[jp]), "dip_t": int(t[jm]), "dip": float(rate[jm])}
+    area = nx * (ny - 2 * TRIM)
+    slopes, corrs = [], []
+    for s in members:
+        x = np.gradient(np.array(s["length"]), t)[jf:] / area
+        y = np.array(s["korteweg"][jf:])
+        slopes.append(float(np.dot(x, y) / max(np.dot(x, x), 1e-300)))
+        corrs.append(float(np.corrcoef(x, y)[0, 1]) if np.std(x) > 0 and np.std(y) > 0 else float("nan"))
+    out["eq21_gamma_fit"] = {"mean": float(np.mean(slopes)), "std": float(np.std(slopes)),
+                             "correlation_mean": float(np.mean(corrs)), "from_t": int(t[jf])}
+    return out
+
+
+def _first_split(s) -> int | None:
+    """Time of the first sample with more than one component in either phase."""
+    for j, tj in enumerate(s["t"]):
+        if not (np.isfinite(s["comp_A"][j]) and np.isfinite(s["comp_B"][j])):
+            return None
+        if s["comp_A"][j] > 1 or s["comp_B"][j] > 1:
+            return int(tj)
+    return None
+
+
 def summarise_paper_runs(runs, times=None) -> dict:
     """Ensemble tables of paper-parameter runs (the output of paper_runs, one
     or more files per case): per case and sample time, the mean and standard
     deviation over (a) the members that stay finite to the end of the run
     and (b) every member still finite at that time (members that fail are
     included up to their last finite sample), so the effect of dropping the
-    failed members on each statistic is visible; and per member the time of
-    its last finite sample."""
+    failed members on each statistic is visible; per member the time of its
+    last finite sample and of its first topology change; and the derived
+    statistics of paper_analysis over the members finite to the end."""
     by_case = {}
     for r in runs:
-        c = by_case.setdefault(r["case"], {"G": r["G"], "storage": r["storage"], "members": [], "seeds": []})
+        c = by_case.setdefault(r["case"], {"G": r["G"], "storage": r["storage"], "members": [], "seeds": [],
+                                           "nx": r.get("params", PAPER)["nx"], "ny": r.get("params", PAPER)["ny"]})
         for k, ser in enumerate(r["members"]):
             c["members"].append(ser)
             c["seeds"].append(r["seed0"] + k)
@@ -403,13 +484,76 @@ def summarise_paper_runs(runs, times=None) -> dict:
         out[case] = {"G": c["G"], "storage": c["storage"], "members": len(mem),
                      "finite_to_end": sum(1 for l in last if l == end),
                      "last_finite_t": {str(s): (t_all[l] if l >= 0 else None) for s, l in zip(c["seeds"], last)},
-                     "tables": rows}
+                     "first_split_t": {str(s): _first_split(ser) for s, ser in zip(c["seeds"], mem)},
+                     "tables": rows,
+                     "analysis": paper_analysis([ser for ser, l in zip(mem, last) if l == end], c["nx"], c["ny"])}
     return out
+
+
+# (key, row label, divisor, decimals) of the markdown tables
+TABLE_ROWS = (("h", "mixing width h", 1.0, 0), ("Ek", "E_k (10⁻⁴)", 1e-4, 2), ("Ep", "E_p (10⁻³)", 1e-3, 2),
+              ("length", "interface length L (10³)", 1e3, 1), ("comp_A", "components of A", 1.0, 0),
+              ("comp_B", "components of B", 1.0, 0), ("umax", "max\\|u\\|", 1.0, 3))
+
+
+def paper_tables_markdown(summary) -> str:
+    """Markdown tables of a paper_runs summary: per case, one row per quantity
+    and member set (those finite to the end; every member finite at t), each
+    cell the mean ± standard deviation and, where it is not every member, the
+    member count in brackets."""
+    out = []
+    for case, c in summary.items():
+        times = list(c["tables"])
+        out.append(f"{case} (G = {c['G']}, {c['storage']}; {c['finite_to_end']} of {c['members']} members "
+                   f"finite to the end):\n")
+        out.append("| quantity | members | " + " | ".join(f"{int(t):,}".replace(",", " ") for t in times) + " |")
+        out.append("|---|---|" + "---|" * len(times))
+        for key, label, div, dec in TABLE_ROWS:
+            if key not in c["tables"][times[0]]:
+                continue
+            for sel, name in (("survivors", "finite to end"), ("finite_at_t", "finite at t")):
+                cells = []
+                for t in times:
+                    s = c["tables"][t][key][sel]
+                    if s["mean"] is None:
+                        cells.append("–")
+                        continue
+                    cell = f"{s['mean'] / div:.{dec}f} ± {s['std'] / div:.{dec}f}"
+                    if s["n"] != c["members"]:
+                        cell += f" [{s['n']}]"
+                    cells.append(cell)
+                out.append(f"| {label} | {name} | " + " | ".join(cells) + " |")
+        failed = {s: t for s, t in c["last_finite_t"].items() if t != int(times[-1])}
+        out.append("")
+        out.append("last finite sample of the failed members (seed: t): " +
+                   (", ".join(f"{s}: {t}" for s, t in failed.items()) if failed else "none"))
+        splits = [t for t in c.get("first_split_t", {}).values() if t is not None]
+        if splits:
+            out.append(f"first topology change: t = {min(splits)} … {max(splits)} ({len(splits)} members)")
+        a = c.get("analysis", {})
+        if "eq17_residual_rel" in a:
+            r, i = a["eq17_residual_rel"], a["eq17_integrals"]
+            out.append(f"Eq. 17 from t = {r['from_t']} (members finite to the end): residual {r['mean']:.2e} of the "
+                       f"summed integrated terms (largest {r['max']:.2e}); integrals " +
+                       ", ".join(f"{k} {v:.3e}" for k, v in i.items()))
+            e = a["eq22"]
+            out.append(f"Eq. 22 from t = {e['from_t']}: viscous vs -eta<omega^2> per sample median "
+                       f"{e['median_rel_diff']:.2%} (largest {e['max_rel_diff']:.1%}); ratio of the time integrals "
+                       f"{e['integral_ratio_min']:.4f} … {e['integral_ratio_max']:.4f}")
+            lr = a["length_rate"]
+            out.append(f"dL/dt of the mean length: peak {lr['peak']:.2f} at t = {lr['peak_t']}, then down to "
+                       f"{lr['dip']:.2f} at t = {lr['dip_t']}")
+            g = a["eq21_gamma_fit"]
+            out.append(f"Eq. 21 fit: gamma_eff = {g['mean']:.5f} ± {g['std']:.5f} (correlation "
+                       f"{g['correlation_mean']:.2f})")
+        out.append("")
+    return "\n".join(out)
 
 
 def main(argv):
     """python -m paper_2101_04847_amd.studies paper-runs CASE MEMBERS SEED0 OUT.json [STEPS [STORAGE]]
-    python -m paper_2101_04847_amd.studies paper-summary OUT.json RUN.json [RUN.json ...]"""
+    python -m paper_2101_04847_amd.studies paper-summary OUT.json RUN.json [RUN.json ...]
+    python -m paper_2101_04847_amd.studies paper-tables SUMMARY.json"""
     import json
     import sys as _sys
 
@@ -421,6 +565,10 @@ def main(argv):
         with open(argv[1], "w") as fh:
             json.dump(summarise_paper_runs(runs), fh, indent=1)
         print(json.dumps({"out": argv[1], "runs": len(runs)}))
+        return
+    if len(argv) == 2 and argv[0] == "paper-tables":
+        with open(argv[1]) as fh:
+            print(paper_tables_markdown(json.load(fh)))
         return
 
     import torch
