@@ -678,6 +678,13 @@ void set_scales(const lb_config *c, const lb_member &mm, Member &M)
             M.scale[s][i] = std::ldexp(1.0f, e);
             M.iscale[s][i] = std::ldexp(1.0f, -e);
         }
+    // the kernels take S_i per weight class (the rule above depends on w_i
+    // only, not on s) and bfloat16 codes as unscaled (e = 0 above: S_i = 1)
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? 1 : 5);
+        M.cscale[k] = M.scale[0][i];
+        M.ciscale[k] = M.iscale[0][i];
+    }
 }
 
 // Field pass of member m (rho_A, rho_B, u_x, u_y of f(t) into device

@@ -36,6 +36,8 @@ struct alignas(256) Member {
     int32_t rho_sstride;     //   and bytes between the two components' density segments
     float scale[2][NQ];      // 16-bit modes: power-of-two scale of the codes; else 1
     float iscale[2][NQ];     // 1 / scale (exact)
+    float cscale[3];         // the same scales per weight class (rest, axis, diagonal): they
+    float ciscale[3];        //   depend on w_i only; the kernels read these
 };
 
 // Storage modes (values equal the LB_F64 .. LB_BF16S constants of lb.h).

@@ -140,12 +140,33 @@ struct RowPull {
     }
 };
 
+// Weight class of population i (0: rest, 1: axis, 2: diagonal); the code
+// scales S_i of the 16-bit modes depend on w_i only.
+__host__ __device__ constexpr int wclass(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 2); }
+
+// x S_i and v / S_i + b in the 16-bit modes.  bfloat16 codes are unscaled
+// (S_i = 1): x * 1 and fma(v, 1, b) = v + b are exact, so skipping them gives
+// the same results.
+template <int ST>
+__device__ __forceinline__ float code_scaled(const Member &M, int i, float x)
+{
+    if constexpr (ST == ST_BF16S) return x;
+    else return x * M.cscale[wclass(i)];
+}
+template <int ST>
+__device__ __forceinline__ float code_unscaled(const Member &M, int i, float v)
+{
+    if constexpr (ST == ST_BF16S) return v;
+    else return v * M.ciscale[wclass(i)];
+}
+
 // 16-bit modes: population i decoded from its code q and the stored density
 // rhat of the site it was stored at, f = w_i rhat + q / S_i.
 template <int ST>
-__device__ __forceinline__ float site_decode(typename Tr<ST>::T q, float rhat, int i, float iscale)
+__device__ __forceinline__ float site_decode(const Member &M, typename Tr<ST>::T q, float rhat, int i)
 {
-    return fmaf(Tr<ST>::value(q), iscale, (float)wgt(i) * rhat);
+    if constexpr (ST == ST_BF16S) return Tr<ST>::value(q) + (float)wgt(i) * rhat;
+    else return fmaf(Tr<ST>::value(q), M.ciscale[wclass(i)], (float)wgt(i) * rhat);
 }
 
 // 16-bit modes: codes of the post-collision populations of component s at
@@ -155,7 +176,7 @@ __device__ __forceinline__ float site_decode(typename Tr<ST>::T q, float rhat, i
 // rounding (sum_i w_i = 1), whatever the rounding of the codes, so the codes
 // carry no systematic mass error.
 template <int ST>
-__device__ __forceinline__ void site_encode(const Member &M, int s, double rho, const float (&post)[NQ],
+__device__ __forceinline__ void site_encode(const Member &M, double rho, const float (&post)[NQ],
                                             typename Tr<ST>::T (&q)[NQ], float &rhat)
 {
     const float r = (float)rho;
@@ -163,8 +184,8 @@ __device__ __forceinline__ void site_encode(const Member &M, int s, double rho, 
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const float d = fmaf(-(float)wgt(i), r, post[i]);
-        q[i] = Tr<ST>::code(d * M.scale[s][i]);
-        e += Tr<ST>::value(q[i]) * M.iscale[s][i];
+        q[i] = Tr<ST>::code(code_scaled<ST>(M, i, d));
+        e += code_unscaled<ST>(M, i, Tr<ST>::value(q[i]));
     }
     rhat = (float)(rho - (double)e);
 }
@@ -188,7 +209,7 @@ __device__ __forceinline__ void pull_site(const void *src, const Member &M, int 
 #pragma unroll
             for (int j = 0; j < NQ; ++j) rh[ORDER[j]] = pr.load_rho(M, s, ORDER[j]);
 #pragma unroll
-            for (int i = 0; i < NQ; ++i) f[s][i] = site_decode<ST>(v[i], rh[i], i, M.iscale[s][i]);
+            for (int i = 0; i < NQ; ++i) f[s][i] = site_decode<ST>(M, v[i], rh[i], i);
         } else {
 #pragma unroll
             for (int i = 0; i < NQ; ++i) f[s][i] = Q::dec(v[i]);
@@ -209,7 +230,7 @@ __device__ __forceinline__ void store_site(const Member &M, rsrc_t wr, unsigned 
         if constexpr (Q::SITE) {
             typename Q::T q[NQ];
             float rhat;
-            site_encode<ST>(M, s, rho[s], post[s], q, rhat);
+            site_encode<ST>(M, rho[s], post[s], q, rhat);
 #pragma unroll
             for (int i = 0; i < NQ; ++i)
                 bstore<LBK_NT_STORE ? CPOL_NT : 0>(q[i], wr, ox, (unsigned)s * wss + (unsigned)i * wis);
@@ -355,7 +376,16 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
                 vxd = ux + M.tau[s] * ax[s];
                 vyd = uy + M.tau[s] * ay[s];
             }
-            const C vx = (C)vxd, vy = (C)vyd, rho = (C)rho_c[s];
+            C vx = (C)vxd, vy = (C)vyd;
+            const C rho = (C)rho_c[s];
+            // Under Guo forcing both components see the same velocity, so
+            // every per-population term of the equilibrium and the source is
+            // the same for both; kept from the first component for the
+            // second they hold ~30 registers across the loop and the fused
+            // pass spills.  The empty asm makes the values opaque per
+            // component so that they are recomputed (same expressions, same
+            // results); with it the FP64 fused Guo pass fits 256 VGPRs.
+            if (FORCING == FORCE_GUO) asm volatile("" : "+v"(vx), "+v"(vy));
             const C omega = (C)M.itau[s];
             const C vv = vx * vx + vy * vy;
             C gcoef = (C)0, fx = (C)0, fy = (C)0, gux = (C)0, guy = (C)0;
@@ -365,6 +395,7 @@ __device__ __forceinline__ void collide_site(const Member &M, const typename Tr<
                 fy = (C)Fy[s];
                 gux = (C)ux;
                 guy = (C)uy;
+                asm volatile("" : "+v"(gux), "+v"(guy));
             }
 #pragma unroll
             for (int i = 0; i < NQ; ++i) {
@@ -1015,9 +1046,9 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 for (int s = 0; s < 2; ++s) {
                     typename Q::T q[NQ];
                     float rhat;
-                    site_encode<ST>(M, s, r1c[s], out1[s], q, rhat);
+                    site_encode<ST>(M, r1c[s], out1[s], q, rhat);
 #pragma unroll
-                    for (int i = 0; i < NQ; ++i) out1[s][i] = site_decode<ST>(q[i], rhat, i, M.iscale[s][i]);
+                    for (int i = 0; i < NQ; ++i) out1[s][i] = site_decode<ST>(M, q[i], rhat, i);
                 }
             }
         } else if (BCY != BC_PERIODIC) {
@@ -1212,7 +1243,7 @@ __global__ void k_scatter(const Member *__restrict__ members, int mi, const doub
                 for (int i = 0; i < NQ; ++i) post[i] = (float)v[s][i];
                 T q[NQ];
                 float rhat;
-                site_encode<ST>(M, s, rho, post, q, rhat);
+                site_encode<ST>(M, rho, post, q, rhat);
 #pragma unroll
                 for (int i = 0; i < NQ; ++i) dst[(int64_t)s * M.sstride + (int64_t)i * M.istride + (int64_t)y * M.ystride + x] = q[i];
                 LBK_GLOBAL char *row = (LBK_GLOBAL char *)dst + (int64_t)y * M.ystride * (int64_t)sizeof(T);
