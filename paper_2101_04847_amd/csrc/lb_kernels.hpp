@@ -899,44 +899,56 @@ constexpr int fused_lds_cap_floats()
 constexpr int DPP_WAVE_SHL1 = 0x130;    // lane l receives lane l + 1 (column x + 1)
 constexpr int DPP_WAVE_SHR1 = 0x138;    // lane l receives lane l - 1 (column x - 1)
 
-template <int CTRL>
+// Lane shifts across the whole wave.  The two edge lanes have no source
+// lane: they keep their own value (ZF = false) or receive 0 (ZF = true, the
+// DPP move's bound control; the compiler then need not copy the source into
+// the destination first).  Edge-lane values never reach an output column
+// (three lanes of halo on either side), so both forms give the same results;
+// the zero fill is what the 16-bit passes run faster with (fewer VALU
+// instructions where VALU is the limit), the keeping form what the FP64 and
+// FP32 passes do.
+template <int CTRL, bool ZF = false>
+__device__ __forceinline__ int lane_shift_b32(int b)
+{
+    if constexpr (ZF) return __builtin_amdgcn_update_dpp(0, b, CTRL, 0xF, 0xF, true);
+    else return __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL, bool ZF = false>
 __device__ __forceinline__ double lane_shift(double v)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
-    const uint32_t nlo = (uint32_t)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
-    const uint32_t nhi = (uint32_t)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    const uint32_t nlo = (uint32_t)lane_shift_b32<CTRL, ZF>((int)(uint32_t)u);
+    const uint32_t nhi = (uint32_t)lane_shift_b32<CTRL, ZF>((int)(uint32_t)(u >> 32));
     return __builtin_bit_cast(double, ((uint64_t)nhi << 32) | nlo);
 }
-template <int CTRL>
+template <int CTRL, bool ZF = false>
 __device__ __forceinline__ float lane_shift(float v)
 {
-    const int b = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, lane_shift_b32<CTRL, ZF>(__builtin_bit_cast(int, v)));
 }
 // value of the column to the left (x - 1) / right (x + 1)
-template <class V> __device__ __forceinline__ V from_left(V v) { return lane_shift<DPP_WAVE_SHR1>(v); }
-template <class V> __device__ __forceinline__ V from_right(V v) { return lane_shift<DPP_WAVE_SHL1>(v); }
+template <bool ZF = false, class V> __device__ __forceinline__ V from_left(V v) { return lane_shift<DPP_WAVE_SHR1, ZF>(v); }
+template <bool ZF = false, class V> __device__ __forceinline__ V from_right(V v) { return lane_shift<DPP_WAVE_SHL1, ZF>(v); }
 
 // Eq. 5 sums of both components from the densities of rows y - 1, y, y + 1
 // of this lane's column; the other columns come from the neighbouring lanes.
-template <bool FACTORED>
+template <bool FACTORED, bool ZF = false>
 __device__ __forceinline__ void sc_sums_lanes(const double (&lo)[2], const double (&mid)[2], const double (&hi)[2],
                                               double (&Sx)[2], double (&Sy)[2])
 {
 #pragma unroll
     for (int o = 0; o < 2; ++o)
-        sc_sum<FACTORED>(from_right(mid[o]), hi[o], from_left(mid[o]), lo[o], from_right(hi[o]), from_left(hi[o]),
-               from_left(lo[o]), from_right(lo[o]), Sx[o], Sy[o]);
+        sc_sum<FACTORED>(from_right<ZF>(mid[o]), hi[o], from_left<ZF>(mid[o]), lo[o], from_right<ZF>(hi[o]),
+                         from_left<ZF>(hi[o]), from_left<ZF>(lo[o]), from_right<ZF>(lo[o]), Sx[o], Sy[o]);
 }
 
 // Streamed value of population i for this lane's column from the same row
 // of step-1 results: shifted by c_x (bounce-back values are not shifted).
-template <int I, class V>
+template <int I, bool ZF = false, class V>
 __device__ __forceinline__ V shift_x(V v)
 {
-    if constexpr (cx(I) > 0) return from_left(v);
-    else if constexpr (cx(I) < 0) return from_right(v);
+    if constexpr (cx(I) > 0) return from_left<ZF>(v);
+    else if constexpr (cx(I) < 0) return from_right<ZF>(v);
     else return v;
 }
 
@@ -960,6 +972,7 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
     using Q = Tr<ST>;
     using T = typename Q::T;
     using C = typename Q::C;
+    constexpr bool ZF = Q::SITE;   // zero-filling lane shifts in the 16-bit passes
     const int ny = M.ny;
     const void *src = M.f[cur];
     void *dst = M.f[cur ^ 1];
@@ -1034,8 +1047,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 rf[s] = in_ap ? r1n[s] : (pz ? 0.0 : r1c[s]);
             }
             double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64>(rb, r1c, rf, Sx, Sy);
-            else sc_sums_lanes<ST != ST_F64>(rf, r1c, rb, Sx, Sy);
+            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, r1c, rf, Sx, Sy);
+            else sc_sums_lanes<ST != ST_F64, ZF>(rf, r1c, rb, Sx, Sy);
             collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, wall_row<BCY>(M, a), [&](int s, int i, C post) {
                 if constexpr (Q::SITE) out1[s][i] = post;
                 else out1[s][i] = Q::dec(Q::enc(post));
@@ -1068,14 +1081,14 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
         const bool bb_b = (BCY != BC_PERIODIC) && !in_a;              // out1 holds bounce-back values
         auto pull_row = [&](int s, C (&v)[NQ]) {
             v[0] = P[s][0];
-            v[1] = shift_x<1>(P[s][1]);
-            v[3] = shift_x<3>(P[s][3]);
+            v[1] = shift_x<1, ZF>(P[s][1]);
+            v[3] = shift_x<3, ZF>(P[s][3]);
             v[FW[0]] = Qv[s][FW[0]];
-            v[FW[1]] = bb_f ? Qv[s][FW[1]] : shift_x<FW[1]>(Qv[s][FW[1]]);
-            v[FW[2]] = bb_f ? Qv[s][FW[2]] : shift_x<FW[2]>(Qv[s][FW[2]]);
+            v[FW[1]] = bb_f ? Qv[s][FW[1]] : shift_x<FW[1], ZF>(Qv[s][FW[1]]);
+            v[FW[2]] = bb_f ? Qv[s][FW[2]] : shift_x<FW[2], ZF>(Qv[s][FW[2]]);
             v[BW[0]] = out1[s][BW[0]];
-            v[BW[1]] = bb_b ? out1[s][BW[1]] : shift_x<BW[1]>(out1[s][BW[1]]);
-            v[BW[2]] = bb_b ? out1[s][BW[2]] : shift_x<BW[2]>(out1[s][BW[2]]);
+            v[BW[1]] = bb_b ? out1[s][BW[1]] : shift_x<BW[1], ZF>(out1[s][BW[1]]);
+            v[BW[2]] = bb_b ? out1[s][BW[2]] : shift_x<BW[2], ZF>(out1[s][BW[2]]);
         };
         // densities of row p (its populations are rebuilt after the
         // collision of row q)
@@ -1098,8 +1111,8 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
                 rf[s] = inside(p) ? r2n[s] : (pz ? 0.0 : r2c[s]);
             }
             double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64>(rb, r2c, rf, Sx, Sy);
-            else sc_sums_lanes<ST != ST_F64>(rf, r2c, rb, Sx, Sy);
+            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, r2c, rf, Sx, Sy);
+            else sc_sums_lanes<ST != ST_F64, ZF>(rf, r2c, rb, Sx, Sy);
             const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
             if constexpr (Q::SITE) {
                 C post[2][NQ];
