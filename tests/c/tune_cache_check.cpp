@@ -1,8 +1,12 @@
 // Host check of the tile-cache file logic of liblb (lb_tune_cache.hpp):
 // store / lookup round trip, several keys in one file, a corrupt file
-// ignored and rewritten, and the cache switched off.  Prints "ok" on success.
+// ignored and rewritten, every truncation and seeded byte corruptions of a
+// valid file read without fault (built with the address and undefined-
+// behaviour sanitizers by the test), and the cache switched off.  Prints
+// "ok" on success.
 //
 //     tune_cache_check <cache-file>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 
@@ -51,6 +55,32 @@ int main(int argc, char **argv)
     lbtune::store("k4", a);
     CHECK(lbtune::lookup("k4", got) && got.th == a.th);
     CHECK(!lbtune::lookup("k2", got));
+    // every truncation of a valid file, and seeded corruptions of it, are
+    // read without fault; a truncated file never yields a choice
+    {
+        const std::string good = lbtune::to_json({{"k1", a}, {"k2", b}, {"k4", a}});
+        for (size_t n = 0; n < good.size(); ++n) {
+            std::map<std::string, lbtune::Choice> m;
+            const std::string cut = good.substr(0, n);
+            const bool ok = lbtune::parse(cut, m);
+            // the closing brace is the last non-space character
+            CHECK(!ok || cut.find_last_not_of(" \n") == good.find_last_not_of(" \n"));
+        }
+        uint32_t r = 12345u;
+        for (int trial = 0; trial < 20000; ++trial) {
+            std::string bad = good;
+            for (int k = 0; k < 1 + trial % 4; ++k) {
+                r = r * 1664525u + 1013904223u;
+                const size_t at = (r >> 8) % bad.size();
+                r = r * 1664525u + 1013904223u;
+                bad[at] = (char)(r >> 24);
+            }
+            std::map<std::string, lbtune::Choice> m;
+            (void)lbtune::parse(bad, m);
+        }
+        std::map<std::string, lbtune::Choice> m;
+        CHECK(lbtune::parse(good, m) && m.size() == 3 && m["k2"].tx == b.tx);
+    }
     // switched off: nothing is read or written
     setenv("LB_TILE_CACHE", "off", 1);
     CHECK(!lbtune::lookup("k4", got));

@@ -290,13 +290,15 @@ def test_c_driver_3d_reports_invalid_configuration(lb, tmp_path):
 def test_tile_cache_file_logic(tmp_path):
     """The persisted tile cache (host code of liblb): round trip of choices
     under several keys, a corrupt file ignored and rewritten, and the cache
-    switched off by LB_TILE_CACHE=off (a C++ check built with g++)."""
+    switched off by LB_TILE_CACHE=off, and truncated or corrupted files read
+    without fault (a C++ check built with g++ under the address and
+    undefined-behaviour sanitizers)."""
     import subprocess
     exe = tmp_path / "tune_cache_check"
     src = os.path.join(ROOT, "tests", "c", "tune_cache_check.cpp")
     inc = os.path.join(ROOT, "paper_2101_04847_amd", "csrc")
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Wextra", "-Werror", "-I", inc, "-o", str(exe), src],
-                   check=True)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-Wall", "-Wextra", "-Werror", "-I", inc, "-o", str(exe), src], check=True)
     r = subprocess.run([str(exe), str(tmp_path / "sub" / "tiles.json")], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip() == "ok"
