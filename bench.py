@@ -6,9 +6,10 @@ velocity-shift BGK collision, store.  Headline workload: the 10000 x 5000
 Rayleigh-Taylor lattice (tau = 1, G = 1.5, g = 1e-5, 32 seeded interface
 modes), FP64 storage and arithmetic, populations resident in HBM, 100-step
 chunks replayed from HIP graphs.  The library times its two passes at
-initialisation and runs the faster per step: one step per kernel pass
-(k_step), or two steps fused in registers (k_step2, populations cross HBM
-once per two steps).
+initialisation and runs the fastest per step: one step per kernel pass
+(k_step), two steps fused in registers (k_step2, populations cross HBM
+once per two steps), or, in the storage modes with FP32 arithmetic, three
+(k_step3).
 
 Prints one JSON line: million lattice updates per second (MLUPS; one update
 = both components at one site for one step), the HBM roofline of the kernel
@@ -27,7 +28,7 @@ energy budget; the 2048 x 1024 lattice's rate under both forcing schemes;
 and a plain device copy timed in the same process as a measured roofline
 denominator.
 
-    python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s] [--spp 0|1|2]
+    python bench.py [--steps K] [--warmup W] [--storage f64|f32|f16s|bf16s] [--spp 0|1|2|3]
     python bench.py --report out.json     # precision and ensemble studies
 """
 from __future__ import annotations
@@ -46,7 +47,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 # 16-bit modes the two FP32 site densities (read + write): the bytes one
 # kernel pass moves per site (per lattice update for single steps)
 BYTES_PER_LU = {"f64": 288, "f32": 144, "f16s": 88, "bf16s": 88}
-KERNEL = {1: "step", 2: "step2"}
+KERNEL = {1: "step", 2: "step2", 3: "step3"}
 METRIC = "MLUPS + % HBM peak, 2-comp D2Q9 Shan-Chen 10000×5000; ensemble MLUPS"
 
 
@@ -85,6 +86,22 @@ def cpu_model() -> str:
         pass
     import platform
     return platform.processor() or "unknown"
+
+
+def kernel_launch_ms(lat, spp: int, stream, n: int = 12) -> float:
+    """Average duration of one pass of spp steps (one kernel launch), timed
+    with events on `stream` around n eager lb_step(spp) calls after one
+    untimed call."""
+    import torch
+
+    lat.step(spp)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        lat.step(spp)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / n
 
 
 def graph_chunk_for(steps: int) -> int:
@@ -462,7 +479,7 @@ def parser() -> argparse.ArgumentParser:
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_LU))
     ap.add_argument("--tile", default="", help="TXxH, e.g. 256x16 (default: timed choice)")
-    ap.add_argument("--spp", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--spp", type=int, default=0, choices=(0, 1, 2, 3),
                     help="steps per kernel pass (0: timed choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the storage variants and the ensemble")
@@ -522,6 +539,12 @@ def main() -> int:
     replays = (args.steps // chunk) if args.steps >= chunk else 0
     eager_steps = args.steps - replays * chunk
     d = lat.diagnostics(0)
+    # the dominant kernel's own launch duration: events around eager passes
+    # of spp steps each (one launch per lb_step call shorter than a graph
+    # chunk) on the lattice's stream, right after the timed region (the
+    # timed region's chunks also hold the passes that take a remainder of a
+    # chunk, e.g. one single step per 100 steps with three-step passes)
+    launch_ms = kernel_launch_ms(lat, spp, stream) if spp < chunk else ms_step * spp
     # cost of the analysis passes (each call synchronises): energy-budget
     # averages and the kinetic-energy balance terms, best of three
     t_diag, t_budget, t_iface, t_comp = [], [], [], []
@@ -547,7 +570,6 @@ def main() -> int:
     # (read + write) x element size per site, i.e. BYTES_PER_LU / spp per
     # lattice update
     kernel = KERNEL[spp]
-    launch_ms = ms_step * spp
     alg_bytes = BYTES_PER_LU[args.storage] * sites
     achieved = alg_bytes / (launch_ms / 1e3) / 1e9
     traffic = measured_traffic(kernel, args.storage, wl.nx, wl.ny, tile=[tx, th])
@@ -566,7 +588,7 @@ def main() -> int:
             "frac_single_step_basis": hbm_frac_single_step_basis(args.storage, ms_step, sites),
             "frac_basis_note": ("frac counts the launch's own bytes (each population read and written once "
                                 f"per launch of {spp} step(s)); frac_single_step_basis counts "
-                                f"{BYTES_PER_LU[args.storage]} B per update, which two fused steps need not move"),
+                                f"{BYTES_PER_LU[args.storage]} B per update, which fused steps need not move"),
             # a plain device copy of 4 GB each way, timed in this process
             "measured_copy_GBs": copy["GBs"], "frac_of_measured_copy": round(achieved / copy["GBs"], 4),
             "measured_copy": copy}
@@ -592,9 +614,12 @@ def main() -> int:
                                       "components_B": comps["B"]}},
     }
     if not args.no_extras:
-        if spp == 2:
+        if spp >= 2:
             log("single-step pass")
             out["single_step"] = variant_line(lb, inputs, args.storage, stream, spp=1)
+        if spp == 3:
+            log("two-step pass")
+            out["two_step"] = variant_line(lb, inputs, args.storage, stream, spp=2)
         out["storage_variants"] = []
         for name in ("f32", "f16s", "bf16s"):
             if name != args.storage:

@@ -132,13 +132,14 @@ typedef struct lb_config {
     int32_t graph_chunk;     /* steps per captured HIP graph (even, >= 2);
                                 0 selects 100; negative disables graphs */
     int32_t steps_per_pass;  /* time steps per kernel pass over the lattice:
-                                1, or 2 (two steps fused in registers, so the
-                                populations cross HBM once per two steps; an odd
-                                remainder of lb_step takes one single step; bit
-                                for bit the same result).  0 chooses by timing
-                                when tile_x == 0, else 1.  With 2, tile_x is
-                                ignored and tile_h (0 = timed) is the band
-                                height of the fused pass */
+                                1, 2 (two steps fused in registers, so the
+                                populations cross HBM once per two steps) or 3
+                                (three steps).  A remainder of lb_step
+                                shorter than a pass takes a two-step pass and
+                                single steps; bit for bit the same result.  0
+                                chooses by timing when tile_x == 0, else 1.
+                                With 2 or 3, tile_x is ignored and tile_h (0 =
+                                timed) is the band height of the fused pass */
 } lb_config;
 
 /* Energy-budget averages at time t (Sec. 3, Eq. 15-18 and Eq. 22).  <.> is
@@ -301,12 +302,12 @@ int32_t lb_set_populations(lb_handle *h, int32_t m, const double *d_f);
 int64_t lb_time(const lb_handle *h);
 
 /* Tile shape of member m in the pass lb_step runs: columns per workgroup
- * (shared by all members: one launch covers them all; 58 output columns per
- * 64-lane wave for two-step passes) and rows per tile (chosen per member size
- * class when tuned). */
+ * (shared by all members: one launch covers them all; 58 / 54 output columns
+ * per 64-lane wave for two- / three-step passes) and rows per tile (chosen per
+ * member size class when tuned). */
 int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *tile_h);
 
-/* Time steps per kernel pass of lb_step: 1 or 2 (negative: error code). */
+/* Time steps per kernel pass of lb_step: 1, 2 or 3 (negative: error code). */
 int32_t lb_steps_per_pass(const lb_handle *h);
 
 /* 1 if lb_init took the pass and tile shapes from the persisted tile cache,

@@ -159,6 +159,32 @@ Step2Fn pick_step2(int storage, int forcing, int bc)
     }
 }
 
+template <int ST, int F>
+Step2Fn step3_for_bc(int bc)
+{
+    switch (bc) {
+        case BC_WALLS: return (Step2Fn)k_step3<ST, F, BC_WALLS>;
+        case BC_PERIODIC: return (Step2Fn)k_step3<ST, F, BC_PERIODIC>;
+        default: return (Step2Fn)k_step3<ST, F, BC_WALLS_WET>;
+    }
+}
+
+template <int ST>
+Step2Fn step3_for(int forcing, int bc)
+{
+    return forcing == LB_FORCE_SHIFT ? step3_for_bc<ST, FORCE_SHIFT>(bc) : step3_for_bc<ST, FORCE_GUO>(bc);
+}
+
+Step2Fn pick_step3(int storage, int forcing, int bc)
+{
+    switch (storage) {
+        case LB_F64: return step3_for<ST_F64>(forcing, bc);
+        case LB_F32: return step3_for<ST_F32>(forcing, bc);
+        case LB_F16S: return step3_for<ST_F16S>(forcing, bc);
+        default: return step3_for<ST_BF16S>(forcing, bc);
+    }
+}
+
 // state conversion depends only on periodic y or walls (an lb_config bc_y)
 template <int ST>
 ScatterFn scatter_for(int bc) { return bc == LB_WALLS ? k_scatter<ST, BC_WALLS> : k_scatter<ST, BC_PERIODIC>; }
@@ -252,8 +278,8 @@ int32_t validate(const lb_config *c)
     if (c->tile_h < 0) return fail(LB_EINVAL, "tile_h = %d must be >= 0", c->tile_h);
     if (c->graph_chunk > 0 && (c->graph_chunk % 2 != 0))
         return fail(LB_EINVAL, "graph_chunk = %d must be even", c->graph_chunk);
-    if (c->steps_per_pass < 0 || c->steps_per_pass > 2)
-        return fail(LB_EINVAL, "steps_per_pass = %d must be 0, 1 or 2", c->steps_per_pass);
+    if (c->steps_per_pass < 0 || c->steps_per_pass > 3)
+        return fail(LB_EINVAL, "steps_per_pass = %d must be 0, 1, 2 or 3", c->steps_per_pass);
     for (int m = 0; m < c->n_members; ++m) {
         const lb_member &mm = c->members[m];
         if (mm.nx < 3 || mm.ny < 3) return fail(LB_EINVAL, "member %d: nx = %d, ny = %d must be >= 3", m, mm.nx, mm.ny);
@@ -299,8 +325,9 @@ struct lb_handle {
     int64_t n_items = 0;
     int kbc = BC_WALLS;             // boundary variant of the step kernels: BC_PERIODIC, BC_WALLS, or
                                     // BC_WALLS_WET when a member has a wall force or psi = 0 beyond walls
-    int steps_per_pass = 1;         // 2: lb_step runs the two-step pass
+    int steps_per_pass = 1;         // 2 / 3: lb_step runs the two- / three-step pass
     int64_t n_items2 = 0;
+    int64_t n_items3 = 0;
     int chunk = 0;
     int chunk_flip = 0;             // buffer parity change of one graph replay
     hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -357,18 +384,43 @@ void plan_tiles2(lb_handle *h, const std::vector<int> &th)
     h->n_items2 = item;
 }
 
+// Bands of the three-step pass: TX3 output columns by th[m] rows.
+void plan_tiles3(lb_handle *h, const std::vector<int> &th)
+{
+    int64_t item = 0;
+    for (size_t m = 0; m < h->dm.size(); ++m) {
+        Member &M = h->dm[m];
+        M.tiles_x3 = (M.nx + TX3 - 1) / TX3;
+        M.tile_h3 = std::max(1, std::min(th[m], M.ny));
+        M.tiles_y3 = (M.ny + M.tile_h3 - 1) / M.tile_h3;
+        M.item3_begin = item;
+        item += (int64_t)M.tiles_x3 * M.tiles_y3;
+        M.item3_end = item;
+    }
+    h->n_items3 = item;
+}
+
 int32_t upload_members(lb_handle *h)
 {
     HIP_TRY(hipMemcpyAsync(dev_members(h), h->dm.data(), sizeof(Member) * h->dm.size(), hipMemcpyHostToDevice, h->stream));
     return LB_OK;
 }
 
-// n steps from buffer cur: two-step passes when selected (an odd remainder
-// takes one single step), else single steps.  Every pass reads buffer cur and
-// writes the other one.
+// n steps from buffer cur: three-step passes when selected, then two-step
+// passes when selected or when two steps remain of three-step passes, then
+// single steps.  Every pass reads buffer cur and writes the other one.
 int32_t launch_steps(lb_handle *h, hipStream_t s, int64_t n, int &cur)
 {
-    if (h->steps_per_pass == 2) {
+    if (h->steps_per_pass == 3) {
+        Step2Fn fn3 = pick_step3(h->cfg.storage, h->cfg.forcing, h->kbc);
+        for (; n >= 3; n -= 3) {
+            hipLaunchKernelGGL(fn3, dim3((unsigned)((h->n_items3 + NW2 - 1) / NW2)), dim3(64 * NW2), 0, s,
+                               (const Member *)dev_members(h),
+                               (int)h->dm.size(), (int64_t)0, h->n_items3, cur);
+            cur ^= 1;
+        }
+    }
+    if (h->steps_per_pass >= 2) {
         Step2Fn fn2 = pick_step2(h->cfg.storage, h->cfg.forcing, h->kbc);
         for (; n >= 2; n -= 2) {
             hipLaunchKernelGGL(fn2, dim3((unsigned)((h->n_items2 + NW2 - 1) / NW2)), dim3(64 * NW2), 0, s,
@@ -479,14 +531,44 @@ int32_t time_shape2(lb_handle *h, const std::vector<int> &th, int reps, float &m
     return LB_OK;
 }
 
+// Time `reps` three-step passes with band heights th; returns milliseconds
+// per step (a third of a pass).
+int32_t time_shape3(lb_handle *h, const std::vector<int> &th, int reps, float &ms)
+{
+    plan_tiles3(h, th);
+    int32_t rc = upload_members(h);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    Step2Fn fn = pick_step3(h->cfg.storage, h->cfg.forcing, h->kbc);
+    auto once = [&]() {
+        hipLaunchKernelGGL(fn, dim3((unsigned)((h->n_items3 + NW2 - 1) / NW2)), dim3(64 * NW2), 0, h->stream,
+                           (const Member *)dev_members(h),
+                           (int)h->dm.size(), (int64_t)0, h->n_items3, h->cur);
+    };
+    once();  // warm-up
+    HIP_TRY(hipEventRecord(a, h->stream));
+    for (int r = 0; r < reps; ++r) once();
+    HIP_TRY(hipEventRecord(b, h->stream));
+    HIP_TRY(hipEventSynchronize(b));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    ms /= (float)(3 * reps);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return LB_OK;
+}
+
 // Tile shapes.  Explicit tile_x / tile_h apply to every member.  Otherwise
 // each candidate is timed with a coordinate search over one tile height per
 // member size class (members of equal nx, ny share it), timing whole
 // ensemble passes that read the current buffer and write the other one (the
 // state is unchanged); the fastest is kept.  The single-step pass always
-// gets a shape (it serves odd remainders and the field pass); the two-step
-// pass is planned when it may be used, and with steps_per_pass == 0 the
-// faster of the two per step is selected.
+// gets a shape (it serves odd remainders and the field pass); the two- and
+// three-step passes are planned when they may be used (the two-step pass also
+// takes two remaining steps of three-step passes), and with
+// steps_per_pass == 0 the fastest per step is selected.
 int32_t search_tiles(lb_handle *h)
 {
     const lb_config &c = h->cfg;
@@ -538,7 +620,7 @@ int32_t search_tiles(lb_handle *h)
     float best1 = 1e30f;
     int best_tx = c.tile_x != 0 ? c.tile_x : 128;
     std::vector<int> best_th(nm, c.tile_h > 0 ? c.tile_h : 16);
-    if (c.tile_x == 0 && spp != 2) {
+    if (c.tile_x == 0 && spp != 2 && spp != 3) {
         std::vector<int> heights = {8, 12, 16, 32, 64, 128};
         if (c.tile_h > 0) heights = {c.tile_h};
         for (int tx : {64, 128, 256, 512}) {
@@ -572,8 +654,25 @@ int32_t search_tiles(lb_handle *h)
             if (rc) return rc;
         }
         plan_tiles2(h, th2);
-        if (spp == 2 || best2 < best1) h->steps_per_pass = 2;
+        if (spp == 2 || (spp == 0 && best2 < best1)) h->steps_per_pass = 2;
+        if (spp == 0 && best2 < best1) best1 = best2;
     }
+
+    // --- three-step pass
+    std::vector<int> th3(nm, c.tile_h > 0 ? c.tile_h : 24);
+    if (spp == 0 || spp == 3) {
+        float best3 = 1e30f;
+        if (c.tile_h == 0 || spp == 0) {
+            std::vector<int> heights = {8, 12, 16, 24, 32, 48, 64, 96};
+            if (c.tile_h > 0) heights = {c.tile_h};
+            int32_t rc = search(heights, 24, [&](const std::vector<int> &thm, float &t) {
+                return time_shape3(h, thm, reps, t);
+            }, th3, best3);
+            if (rc) return rc;
+        }
+        if (spp == 3 || best3 < best1) h->steps_per_pass = 3;
+    }
+    plan_tiles3(h, th3);
     return upload_members(h);
 }
 
@@ -626,15 +725,17 @@ int32_t choose_tiles(lb_handle *h)
     size_classes(h, shapes, cls);
     const std::string key = tune_key(h);
     lbtune::Choice ch;
-    if (lbtune::lookup(key, ch) && (ch.spp == 1 || ch.spp == 2) && tx_index(ch.tx) >= 0 &&
-        ch.th.size() == shapes.size() && ch.th2.size() == shapes.size()) {
-        std::vector<int> th(h->dm.size()), th2(h->dm.size());
+    if (lbtune::lookup(key, ch) && ch.spp >= 1 && ch.spp <= 3 && tx_index(ch.tx) >= 0 &&
+        ch.th.size() == shapes.size() && ch.th2.size() == shapes.size() && ch.th3.size() == shapes.size()) {
+        std::vector<int> th(h->dm.size()), th2(h->dm.size()), th3(h->dm.size());
         for (size_t m = 0; m < h->dm.size(); ++m) {
             th[m] = std::max(1, ch.th[cls[m]]);
             th2[m] = std::max(1, ch.th2[cls[m]]);
+            th3[m] = std::max(1, ch.th3[cls[m]]);
         }
         plan_tiles(h, ch.tx, th);
         plan_tiles2(h, th2);
+        plan_tiles3(h, th3);
         h->steps_per_pass = ch.spp;
         h->tiles_cached = 1;
         return upload_members(h);
@@ -645,9 +746,11 @@ int32_t choose_tiles(lb_handle *h)
     ch.tx = h->tile_x;
     ch.th.assign(shapes.size(), 0);
     ch.th2.assign(shapes.size(), 0);
+    ch.th3.assign(shapes.size(), 0);
     for (size_t m = 0; m < h->dm.size(); ++m) {
         ch.th[cls[m]] = h->dm[m].tile_h;
         ch.th2[cls[m]] = h->dm[m].tile_h2;
+        ch.th3[cls[m]] = h->dm[m].tile_h3;
     }
     lbtune::store(key, ch);
     return LB_OK;
@@ -827,6 +930,7 @@ int32_t lb_init(const lb_config *cfg, void *d_workspace, size_t bytes, void *hip
     if (cfg->bc_y == LB_PERIODIC_Y) h->kbc = BC_PERIODIC;
     plan_tiles(h, cfg->tile_x ? cfg->tile_x : 64, std::vector<int>(cfg->n_members, cfg->tile_h ? cfg->tile_h : 16));
     plan_tiles2(h, std::vector<int>(cfg->n_members, 12));
+    plan_tiles3(h, std::vector<int>(cfg->n_members, 24));
     if ((rc = upload_members(h))) return bail(rc);
 
     // initial state f(0) = w_i rho_s(0), written as the pre-streamed buffer
@@ -1095,8 +1199,9 @@ int32_t lb_tile_shape(const lb_handle *h, int32_t m, int32_t *tile_x, int32_t *t
 {
     if (!is_live(h)) return fail(LB_ESTATE, "handle is not live");
     if (m < 0 || m >= (int32_t)h->dm.size()) return fail(LB_EINVAL, "member %d out of range", m);
-    if (tile_x) *tile_x = h->steps_per_pass == 2 ? TX2 : h->tile_x;
-    if (tile_h) *tile_h = h->steps_per_pass == 2 ? h->dm[m].tile_h2 : h->dm[m].tile_h;
+    const int spp = h->steps_per_pass;
+    if (tile_x) *tile_x = spp == 3 ? TX3 : (spp == 2 ? TX2 : h->tile_x);
+    if (tile_h) *tile_h = spp == 3 ? h->dm[m].tile_h3 : (spp == 2 ? h->dm[m].tile_h2 : h->dm[m].tile_h);
     return LB_OK;
 }
 

@@ -24,6 +24,10 @@ struct alignas(256) Member {
     int32_t pad_;
     int64_t item2_begin;     // first work item of this member in the two-step launch
     int64_t item2_end;
+    int32_t tiles_x3, tiles_y3, tile_h3;   // tiles of the three-step pass
+    int32_t pad3_;
+    int64_t item3_begin;     // first work item of this member in the three-step launch
+    int64_t item3_end;
     void *f[2];              // ping-pong population buffers, row blocks [y][s][i][pitch]
     double tau[2], itau[2];  // relaxation times and their reciprocals
     double G;                // Shan-Chen coupling

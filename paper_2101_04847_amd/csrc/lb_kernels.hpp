@@ -25,7 +25,8 @@
 //            band computing step t -> t+1 in registers and, two rows behind,
 //            step t+1 -> t+2 from the neighbouring lanes' results (DPP
 //            shifts); populations cross HBM once per two steps.
-// Both evaluate every site through collide_site, so they agree bit for bit.
+//   k_step3  three steps per pass, the same march with a third stage.
+// All evaluate every site through collide_site, so they agree bit for bit.
 //
 // In the FP64 mode every expression is evaluated in the order of the
 // definitions (sums over i in index order, no contraction), so the step is
@@ -1200,6 +1201,291 @@ k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_
 #endif
         if (down) march2<ST, FORCING, BCY, -1>(M, cur, y0, nrows, c, store_ok);
         else march2<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Three steps per pass: the march of the two-step pass with a third stage
+// behind the second.  Per march index k (step-1 row a = first - 4 DIR + k DIR):
+//   step 1 collides row a (rho(t) of a - DIR, a, a + DIR);
+//   step 2 pulls row a - DIR from the step-1 rows a - 2 DIR, a - DIR, a and
+//   collides row q = a - 2 DIR, whose results stay in registers;
+//   step 3 pulls row q - DIR from the step-2 rows q - 2 DIR, q - DIR, q and
+//   collides row r = a - 4 DIR, which it stores.
+// Steps 1 and 2 keep their results in the stored form (decoded as the next
+// pass would pull them), so the pass equals three single steps bit for bit.
+// A work item covers TX3 output columns (five lanes of halo on either side:
+// each step's pull and Eq. 5 sums reach one lane further) and a band of rows
+// whose f(t) rows extend five rows beyond it on either side.
+constexpr int TX3 = 54;
+
+template <int ST, int FORCING, int BCY, int DIR>
+__device__ __forceinline__ void march3(const Member &M, int cur, int y0, int nrows, int c, bool store_ok)
+{
+    using Q = Tr<ST>;
+    using T = typename Q::T;
+    using C = typename Q::C;
+    constexpr bool ZF = Q::SITE;
+    const int ny = M.ny;
+    const void *src = M.f[cur];
+    void *dst = M.f[cur ^ 1];
+    const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
+    const unsigned ox = (unsigned)c * (unsigned)sizeof(T);
+    const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
+    const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
+    auto inside = [&](int v) { return BCY == BC_PERIODIC || (v >= 0 && v < ny); };
+    const bool pz = BCY == BC_WALLS_WET && M.psi_zero;
+    auto wrap = [&](int v) {
+        if (BCY == BC_PERIODIC) {
+            v %= ny;
+            if (v < 0) v += ny;
+        }
+        return v;
+    };
+    constexpr int FW[3] = {DIR > 0 ? 2 : 4, DIR > 0 ? 5 : 7, DIR > 0 ? 6 : 8};
+    constexpr int BW[3] = {DIR > 0 ? 4 : 2, DIR > 0 ? 7 : 5, DIR > 0 ? 8 : 6};
+
+    C fa[2][NQ], fb[2][NQ];     // pulled f(t) of rows a and a + DIR
+    C g[2][NQ];                 // pulled f(t+1) of row q (then of row a - DIR)
+    C hh[2][NQ];                // pulled f(t+2) of row r (then of row q - DIR)
+    C P[2][NQ], Qv[2][NQ];      // step-1 results of rows a - DIR (c_y = 0, DIR) and a - 2 DIR (c_y = DIR)
+    C P2[2][NQ], Qv2[2][NQ];    // step-2 results of rows q - DIR and q - 2 DIR
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            fa[s][i] = fb[s][i] = g[s][i] = hh[s][i] = P[s][i] = Qv[s][i] = P2[s][i] = Qv2[s][i] = (C)0;
+    double r1m[2] = {0.0, 0.0}, r1c[2] = {0.0, 0.0};   // rho(t) of rows a - DIR, a
+    double r2m[2] = {0.0, 0.0}, r2c[2] = {0.0, 0.0};   // rho(t+1) of rows q - DIR, q
+    double r3m[2] = {0.0, 0.0}, r3c[2] = {0.0, 0.0};   // rho(t+2) of rows r - DIR, r
+
+    const int first = DIR > 0 ? y0 : y0 + nrows - 1;
+    const int a0 = first - 4 * DIR;
+    if (inside(a0 - DIR)) {
+        C hf[2][NQ];
+        pull_site<ST, BCY>(src, M, wrap(a0 - DIR), c, hf);
+        r1m[0] = density(hf[0]);
+        r1m[1] = density(hf[1]);
+    }
+    if (inside(a0)) {
+        pull_site<ST, BCY>(src, M, wrap(a0), c, fa);
+        r1c[0] = density(fa[0]);
+        r1c[1] = density(fa[1]);
+    }
+    if (inside(a0 + DIR)) pull_site<ST, BCY>(src, M, wrap(a0 + DIR), c, fb);
+    const int K = nrows + 8;
+
+    // Eq. 5 sums from the densities of the rows behind (rb), at (rc) and
+    // ahead of (rf) a row in the march
+    auto sums = [&](const double (&rb)[2], const double (&rc)[2], const double (&rf)[2], double (&Sx)[2],
+                    double (&Sy)[2]) {
+        if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, rc, rf, Sx, Sy);
+        else sc_sums_lanes<ST != ST_F64, ZF>(rf, rc, rb, Sx, Sy);
+    };
+    // collision of a row whose results stay in registers, in the stored form
+    auto collide_keep = [&](const C (&f)[2][NQ], const double (&rho)[2], const double (&Sx)[2], const double (&Sy)[2],
+                            int row, C (&out)[2][NQ]) {
+        collide_site<ST, FORCING>(M, f, rho, Sx, Sy, wall_row<BCY>(M, row), [&](int s, int i, C post) {
+            if constexpr (Q::SITE) out[s][i] = post;
+            else out[s][i] = Q::dec(Q::enc(post));
+        });
+        if constexpr (Q::SITE) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                typename Q::T qc[NQ];
+                float rhat;
+                site_encode<ST>(M, rho[s], out[s], qc, rhat);
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) out[s][i] = site_decode<ST>(M, qc[i], rhat, i);
+            }
+        }
+    };
+    // pull of a row from rows of results: Qr the row behind (its c_y = DIR
+    // populations), Pr the row itself (c_y = 0), Or the row ahead (c_y = -DIR);
+    // bounce-back values (bbf: Qr holds them, bbb: Or holds them) are not shifted
+    auto pull_rows = [&](int s, const C (&Qr)[2][NQ], const C (&Pr)[2][NQ], const C (&Or)[2][NQ], bool bbf, bool bbb,
+                         C (&v)[NQ]) {
+        v[0] = Pr[s][0];
+        v[1] = shift_x<1, ZF>(Pr[s][1]);
+        v[3] = shift_x<3, ZF>(Pr[s][3]);
+        v[FW[0]] = Qr[s][FW[0]];
+        v[FW[1]] = bbf ? Qr[s][FW[1]] : shift_x<FW[1], ZF>(Qr[s][FW[1]]);
+        v[FW[2]] = bbf ? Qr[s][FW[2]] : shift_x<FW[2], ZF>(Qr[s][FW[2]]);
+        v[BW[0]] = Or[s][BW[0]];
+        v[BW[1]] = bbb ? Or[s][BW[1]] : shift_x<BW[1], ZF>(Or[s][BW[1]]);
+        v[BW[2]] = bbb ? Or[s][BW[2]] : shift_x<BW[2], ZF>(Or[s][BW[2]]);
+    };
+    // beyond a wall psi is the wall row's (mirror) or zero
+    auto beyond = [&](bool in, const double (&r)[2], const double (&wall)[2], double (&out)[2]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) out[s] = in ? r[s] : (pz ? 0.0 : wall[s]);
+    };
+    // rotate a stage's results: row x becomes the row behind the next pull
+    auto rotate = [&](C (&Pr)[2][NQ], C (&Qr)[2][NQ], const C (&out)[2][NQ], bool bb_next) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Qr[s][FW[j]] = bb_next ? out[s][opp(FW[j])] : Pr[s][FW[j]];
+            Pr[s][0] = out[s][0];
+            Pr[s][1] = out[s][1];
+            Pr[s][3] = out[s][3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Pr[s][FW[j]] = out[s][FW[j]];
+        }
+    };
+
+    auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
+        const int a = a0 + k * DIR;
+        const bool in_a = inside(a), in_am = inside(a - DIR), in_ap = inside(a + DIR);
+        const bool load_next = k + 1 < K && inside(a + 2 * DIR);
+        const double r1n[2] = {density(f1n[0]), density(f1n[1])};
+        // --- step 1 at row a
+        C out1[2][NQ];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) out1[s][i] = (C)0;
+        if (in_a) {
+            double rb[2], rf[2], Sx[2], Sy[2];
+            beyond(in_am, r1m, r1c, rb);
+            beyond(in_ap, r1n, r1c, rf);
+            sums(rb, r1c, rf, Sx, Sy);
+            collide_keep(f1c, r1c, Sx, Sy, a, out1);
+        } else if (BCY != BC_PERIODIC) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) out1[s][BW[j]] = P[s][opp(BW[j])];
+        }
+        if (load_next) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
+        // --- step 2: row p = a - DIR pulled from the step-1 rows
+        const int p = a - DIR;
+        const bool pull_p = k >= 2 && inside(p);
+        const bool bb_f = (BCY != BC_PERIODIC) && !inside(p - DIR);
+        const bool bb_b = (BCY != BC_PERIODIC) && !in_a;
+        double r2n[2] = {0.0, 0.0};
+        if (pull_p) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                C v[NQ];
+                pull_rows(s, Qv, P, out1, bb_f, bb_b, v);
+                r2n[s] = density(v);
+            }
+        }
+        // --- step 2 collides row q = a - 2 DIR (rows first - 2 DIR on)
+        const int q = a - 2 * DIR;
+        const bool in_q = inside(q);
+        C out2[2][NQ];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) out2[s][i] = (C)0;
+        if (k >= 4) {
+            if (in_q) {
+                double rb[2], rf[2], Sx[2], Sy[2];
+                beyond(inside(q - DIR), r2m, r2c, rb);
+                beyond(inside(p), r2n, r2c, rf);
+                sums(rb, r2c, rf, Sx, Sy);
+                collide_keep(g, r2c, Sx, Sy, q, out2);
+            } else if (BCY != BC_PERIODIC) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) out2[s][BW[j]] = P2[s][opp(BW[j])];
+            }
+        }
+        if (pull_p) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) pull_rows(s, Qv, P, out1, bb_f, bb_b, g[s]);
+        }
+        // --- step 3: row p3 = q - DIR pulled from the step-2 rows
+        const int p3 = q - DIR;
+        const bool pull_p3 = k >= 6 && inside(p3);
+        const bool bb3_f = (BCY != BC_PERIODIC) && !inside(p3 - DIR);
+        const bool bb3_b = (BCY != BC_PERIODIC) && !in_q;
+        double r3n[2] = {0.0, 0.0};
+        if (pull_p3) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                C v[NQ];
+                pull_rows(s, Qv2, P2, out2, bb3_f, bb3_b, v);
+                r3n[s] = density(v);
+            }
+        }
+        // --- step 3 collides and stores row r = a - 4 DIR (inside the band from k = 8)
+        if (k >= 8) {
+            const int r = a - 4 * DIR;
+            double rb[2], rf[2], Sx[2], Sy[2];
+            beyond(inside(r - DIR), r3m, r3c, rb);
+            beyond(inside(p3), r3n, r3c, rf);
+            sums(rb, r3c, rf, Sx, Sy);
+            const rsrc_t wr = row_rsrc(dst, wrap(r), row_bytes);
+            if constexpr (Q::SITE) {
+                C post[2][NQ];
+                collide_site<ST, FORCING>(M, hh, r3c, Sx, Sy, wall_row<BCY>(M, r),
+                                          [&](int s, int i, C pv) { post[s][i] = pv; });
+                if (store_ok) store_site<ST>(M, wr, ox, c, wis, wss, r3c, post);
+            } else {
+                collide_site<ST, FORCING>(M, hh, r3c, Sx, Sy, wall_row<BCY>(M, r), [&](int s, int i, C post) {
+                    if (store_ok)
+                        bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
+                });
+            }
+        }
+        if (pull_p3) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) pull_rows(s, Qv2, P2, out2, bb3_f, bb3_b, hh[s]);
+        }
+        // --- rotate both stages' results and the densities
+        rotate(P, Qv, out1, (BCY != BC_PERIODIC) && in_a && !in_am);
+        rotate(P2, Qv2, out2, (BCY != BC_PERIODIC) && in_q && !inside(q - DIR));
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            r1m[s] = r1c[s];
+            r1c[s] = r1n[s];
+            r2m[s] = r2c[s];
+            r2c[s] = r2n[s];
+            r3m[s] = r3c[s];
+            r3c[s] = r3n[s];
+        }
+    };
+    int k = 0;
+    for (; k + 2 <= K; k += 2) {
+        iter(k, fa, fb);
+        iter(k + 1, fb, fa);
+    }
+    if (k < K) iter(k, fa, fb);
+}
+
+// FP32 arithmetic: about 210 VGPRs, two waves per SIMD.  FP64: the two sets
+// of pulled rows and two stages of results need about 350 registers, so the
+// pass runs one wave per SIMD (256 VGPRs and the rest in AGPRs, no scratch);
+// with taller bands it is still faster per step than the two-step pass at two
+// waves.
+template <int ST, int FORCING, int BCY>
+__global__ void __launch_bounds__(64 * NW2) __attribute__((amdgpu_waves_per_eu(ST == ST_F64 ? 1 : 2)))
+k_step3(const Member *__restrict__ members, int n_members, int64_t item0, int64_t n_items, int cur)
+{
+    // work items and their order as in k_step2
+    const int lane = threadIdx.x & 63;
+    const int wave = NW2 == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int64_t item = item0 + (int64_t)blockIdx.x * NW2 + wave; item < item0 + n_items;
+         item += (int64_t)gridDim.x * NW2) {
+        int m = 0;
+        while (m + 1 < n_members && members[m].item3_end <= item) ++m;
+        const Member &M = members[m];
+        const int64_t t = item - M.item3_begin;
+        const int tx = (int)(t % M.tiles_x3);
+        const int ty = (int)(t / M.tiles_x3);
+        const int x0 = tx * TX3;
+        const int y0 = ty * M.tile_h3;
+        const int nrows = min(M.tile_h3, M.ny - y0);
+        const int xl = x0 - 5 + lane;
+        int c = xl % M.nx;
+        if (c < 0) c += M.nx;
+        const bool store_ok = lane >= 5 && lane < 5 + TX3 && xl < M.nx;
+        if ((ty & 1) != 0) march3<ST, FORCING, BCY, -1>(M, cur, y0, nrows, c, store_ok);
+        else march3<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
     }
 }
 

@@ -5,9 +5,10 @@
 // requested pass and tile options and the member lattice sizes.  Its result
 // is kept in a small JSON file so that later processes skip the timing:
 //
-//   { "<key>": {"spp": 2, "tx": 128, "th": [16, 32], "th2": [8, 7]}, ... }
+//   { "<key>": {"spp": 2, "tx": 128, "th": [16, 32], "th2": [8, 7], "th3": [12, 12]}, ... }
 //
-// with th / th2 the band heights of the single-step and the two-step pass
+// with th / th2 / th3 the band heights of the single-step, the two-step and
+// the three-step pass
 // per size class (in the order the classes first appear among the members).
 // The file is LB_TILE_CACHE if that is set ("off" or empty disables the
 // cache), else $XDG_CACHE_HOME/liblb/tiles.json or ~/.cache/liblb/tiles.json.
@@ -30,7 +31,7 @@ namespace lbtune {
 
 struct Choice {
     int spp = 0, tx = 0;
-    std::vector<int> th, th2;
+    std::vector<int> th, th2, th3;
 };
 
 inline std::string cache_path()
@@ -129,6 +130,7 @@ inline bool parse(const std::string &text, std::map<std::string, Choice> &out)
             else if (f == "tx") c.tx = r.num();
             else if (f == "th") c.th = r.arr();
             else if (f == "th2") c.th2 = r.arr();
+            else if (f == "th3") c.th3 = r.arr();
             else r.ok = false;
         } while (r.ok && r.eat(','));
         r.need('}');
@@ -151,7 +153,7 @@ inline std::string to_json(const std::map<std::string, Choice> &m)
     for (const auto &kv : m) {
         o += " \"" + kv.first + "\": {\"spp\": " + std::to_string(kv.second.spp) + ", \"tx\": " +
              std::to_string(kv.second.tx) + ", \"th\": " + arr(kv.second.th) + ", \"th2\": " + arr(kv.second.th2) +
-             "}" + (++k < m.size() ? ",\n" : "\n");
+             ", \"th3\": " + arr(kv.second.th3) + "}" + (++k < m.size() ? ",\n" : "\n");
     }
     return o + "}\n";
 }

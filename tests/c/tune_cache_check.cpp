@@ -31,17 +31,19 @@ int main(int argc, char **argv)
     a.tx = 128;
     a.th = {16, 32};
     a.th2 = {7, 9};
+    a.th3 = {12, 16};
     b.spp = 1;
     b.tx = 256;
     b.th = {12};
     b.th2 = {12};
+    b.th3 = {10};
     CHECK(!lbtune::lookup("k1", got));
     lbtune::store("gfx950:sramecc+:xnack-|cu256|st0|f0|bc0|spp0|tx0|th0|100x50,100x50", a);
     lbtune::store("k2", b);
     CHECK(lbtune::lookup("gfx950:sramecc+:xnack-|cu256|st0|f0|bc0|spp0|tx0|th0|100x50,100x50", got));
-    CHECK(got.spp == 2 && got.tx == 128 && got.th == a.th && got.th2 == a.th2);
+    CHECK(got.spp == 2 && got.tx == 128 && got.th == a.th && got.th2 == a.th2 && got.th3 == a.th3);
     CHECK(lbtune::lookup("k2", got));
-    CHECK(got.spp == 1 && got.tx == 256 && got.th == b.th && got.th2 == b.th2);
+    CHECK(got.spp == 1 && got.tx == 256 && got.th == b.th && got.th2 == b.th2 && got.th3 == b.th3);
     CHECK(!lbtune::lookup("k3", got));
     // overwrite a key
     b.tx = 64;

@@ -77,7 +77,7 @@ def test_workspace_bytes_accounts_for_storage(lb):
     (dict(diag_trim=0), "diag_trim"),
     (dict(tile_x=100), "tile_x"),
     (dict(graph_chunk=7), "graph_chunk"),
-    (dict(steps_per_pass=3), "steps_per_pass"),
+    (dict(steps_per_pass=4), "steps_per_pass"),
     (dict(steps_per_pass=-1), "steps_per_pass"),
 ])
 def test_config_validation(lb, kw, msg):

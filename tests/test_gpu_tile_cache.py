@@ -34,7 +34,7 @@ def test_cached_init_matches_timed_init(lb, storage, tmp_path, monkeypatch):
     assert len(rec) == 1
     (key, choice), = rec.items()
     assert key.startswith("gfx950") and "700x300,700x300,512x200" in key
-    assert len(choice["th"]) == len(choice["th2"]) == 2          # two size classes
+    assert len(choice["th"]) == len(choice["th2"]) == len(choice["th3"]) == 2   # two size classes
     b = lb.Lattice(mem, storage=st, poison=True)
     assert b.tiles_cached
     assert b.steps_per_pass == a.steps_per_pass == choice["spp"]
