@@ -663,7 +663,7 @@ int32_t search_tiles(lb_handle *h)
     if (spp == 0 || spp == 3) {
         float best3 = 1e30f;
         if (c.tile_h == 0 || spp == 0) {
-            std::vector<int> heights = {8, 12, 16, 24, 32, 48, 64, 96};
+            std::vector<int> heights = {8, 12, 16, 24, 32, 48, 64, 96, 128, 160};
             if (c.tile_h > 0) heights = {c.tile_h};
             int32_t rc = search(heights, 24, [&](const std::vector<int> &thm, float &t) {
                 return time_shape3(h, thm, reps, t);
