@@ -42,6 +42,7 @@ CASES = [
     (70, 33, 61, 0, 0, 2, (1.0, 1.0), 1.5, 1e-4),     # two-step passes and a final single step
     (70, 33, 20, 1, 1, 1, (0.9, 0.9), 1.2, 1e-4),     # Guo forcing (equal taus), periodic y, single steps
     (130, 21, 40, 0, 0, 0, (0.53, 0.53), 0.1381, 9e-6),   # the paper's immiscible tau and G, timed pass
+    (90, 40, 50, 0, 0, 3, (1.0, 0.8), 1.5, 1e-4),     # three-step passes, a two-step remainder, unequal taus
 ]
 
 
