@@ -75,6 +75,22 @@ def measured_traffic(kernel: str, storage: str, nx: int, ny: int, tile=None):
     return None
 
 
+def measured_sq(kernel: str, storage: str):
+    """Shader-sequencer shares of the kernel (VALU busy, cycles issuing,
+    cycles waiting on a dependency) from the committed counter summary, if
+    taken from the current kernel sources; else None."""
+    from paper_2101_04847_amd.profiling import kernel_source_hash
+    path = os.path.join(ROOT, "profiles", "sq_counters_10000x5000.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        recs = json.load(fh)
+    for rec in recs:
+        if rec.get("kernel") == kernel and rec.get("storage") == storage and rec.get("source_hash") == kernel_source_hash():
+            return {k: rec[k] for k in ("valu_busy", "issue_any", "wait_dependency", "tile")}
+    return None
+
+
 def cpu_model() -> str:
     """The host CPU's model name (first entry of /proc/cpuinfo)."""
     try:
@@ -589,6 +605,10 @@ def main() -> int:
             "frac_basis_note": ("frac counts the launch's own bytes (each population read and written once "
                                 f"per launch of {spp} step(s)); frac_single_step_basis counts "
                                 f"{BYTES_PER_LU[args.storage]} B per update, which fused steps need not move"),
+            # what limits the kernel, from its committed shader-sequencer counters
+            # (profiles/sq_counters_10000x5000.md): a memory-bound pass waits on
+            # loads; the one-wave-per-SIMD three-step pass issues in most cycles
+            "sq_counters": measured_sq(kernel, args.storage),
             # a plain device copy of 4 GB each way, timed in this process
             "measured_copy_GBs": copy["GBs"], "frac_of_measured_copy": round(achieved / copy["GBs"], 4),
             "measured_copy": copy}
