@@ -953,27 +953,48 @@ __device__ __forceinline__ V shift_x(V v)
     else return v;
 }
 
-// One band of the two-step pass, marching in direction DIR (+1: up).  Row
-// roles for the march index k (step-1 row a = first - 2 DIR + k DIR):
-//   step 1 collides row a (needs rho(t) of a - DIR, a, a + DIR);
-//   step 2 pulls row p = a - DIR from the step-1 rows a - 2 DIR (its c_y = DIR
-//   populations), p (c_y = 0) and a (c_y = -DIR), then collides row
-//   q = a - 2 DIR, whose densities rho(t+1) of q - DIR, q, q + DIR = p are then
-//   known.
-// The populations of row a + 2 DIR are requested right after the step-1
+// One band of a pass of NS fused steps (NS = 2 or 3), marching in direction
+// DIR (+1: up).  Per march index k (step-1 row a = first - 2 (NS - 1) DIR +
+// k DIR) and stage j = 1 .. NS:
+//   stage 1 collides row a from the pulled f(t) (rho(t) of a - DIR, a, a + DIR);
+//   stage j > 1 pulls row p_j = a - (2 j - 3) DIR from the results of stage
+//   j - 1 (rows p_j - DIR: its c_y = DIR populations, p_j: c_y = 0, and
+//   p_j + DIR: c_y = -DIR), whose densities are then known, and collides row
+//   q_j = a - 2 (j - 1) DIR, whose neighbours' densities are known from this
+//   and the two previous pulls.  The results of every stage but the last stay
+//   in registers, in the stored form (encoded and decoded as the next pass
+//   would pull them), so the pass equals NS single steps bit for bit; the
+//   last stage's are stored.
+// Stage j collides rows from k = 4 (j - 1) on: the last stage covers the band,
+// each earlier stage the rows the next one needs (two more on either side).
+// The populations of row a + 2 DIR are requested right after the stage-1
 // collision of row a, into the registers it has just consumed (two rotating
-// sets); the last step-1 row requests none.
-// Only one pulled f(t+1) row is held in registers: row p's densities are
-// summed from its sources, and its populations are rebuilt (the same DPP
-// moves again) after the collision of row q.  This keeps the FP64 pass within
-// 256 VGPRs, two waves per SIMD.
-template <int ST, int FORCING, int BCY, int DIR>
-__device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nrows, int c, bool store_ok)
+// sets); the last step-1 row requests none.  Only one pulled input row per
+// stage is held: row p_j's densities are summed from its sources, and its
+// populations are rebuilt (the same DPP moves again) after the collision of
+// row q_j.  This keeps the FP64 two-step pass within 256 VGPRs, two waves per
+// SIMD.
+// A work item covers 66 - 4 NS output columns (2 NS - 1 lanes of halo on
+// either side: each step's pull and Eq. 5 sums reach one lane further, and
+// the first step's pull comes from memory) and a band whose f(t) rows extend
+// 2 NS - 1 rows beyond it on either side.
+template <int NS> constexpr int tx_of_pass() { return 66 - 4 * NS; }
+static_assert(tx_of_pass<2>() == TX2, "the two-step window");
+
+template <int ST, int FORCING, int BCY, int DIR, int NS>
+__device__ __forceinline__ void marchN(const Member &M, int cur, int y0, int nrows, int c, bool store_ok)
 {
+    static_assert(NS == 2 || NS == 3, "two or three fused steps");
     using Q = Tr<ST>;
     using T = typename Q::T;
     using C = typename Q::C;
-    constexpr bool ZF = Q::SITE;   // zero-filling lane shifts in the 16-bit passes
+    // zero-filling lane shifts (no copy of each shifted value first): the
+    // 16-bit two-step passes and every three-step pass are bound by their
+    // instruction issue (FP64 three-step 33.8 -> 37.1 GLUPS, FP32 66.9 ->
+    // 68.7 at 10000 x 5000); the memory-bound FP64 and FP32 two-step passes
+    // measured no faster with it
+    constexpr bool ZF = NS >= 3 || Q::SITE;
+    constexpr int NK = NS - 1;              // stages whose results stay in registers
     const int ny = M.ny;
     const void *src = M.f[cur];
     void *dst = M.f[cur ^ 1];
@@ -982,7 +1003,6 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
     const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
     const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
     auto inside = [&](int v) { return BCY == BC_PERIODIC || (v >= 0 && v < ny); };
-    // psi beyond a wall: that of the wall row (mirror) or zero
     const bool pz = BCY == BC_WALLS_WET && M.psi_zero;
     auto wrap = [&](int v) {
         if (BCY == BC_PERIODIC) {
@@ -991,165 +1011,193 @@ __device__ __forceinline__ void march2(const Member &M, int cur, int y0, int nro
         }
         return v;
     };
-    // populations whose source row lies ahead of (c_y = DIR) or behind
-    // (c_y = -DIR) the pulled row in the march
     constexpr int FW[3] = {DIR > 0 ? 2 : 4, DIR > 0 ? 5 : 7, DIR > 0 ? 6 : 8};
     constexpr int BW[3] = {DIR > 0 ? 4 : 2, DIR > 0 ? 7 : 5, DIR > 0 ? 8 : 6};
 
     C fa[2][NQ], fb[2][NQ];     // pulled f(t) of rows a and a + DIR
-    C g[2][NQ];                 // pulled f(t+1) of row q (then of row p)
-    C P[2][NQ], Qv[2][NQ];      // step-1 results of rows a - DIR (c_y = 0, DIR) and a - 2 DIR (c_y = DIR)
+    C g[NK][2][NQ];             // g[j]: pulled input of stage j + 2 (row q_{j+2}, then the row it pulls next)
+    C P[NK][2][NQ], Qv[NK][2][NQ];   // results of stage j + 1: the row behind its latest (c_y = 0, DIR) and the one before (c_y = DIR)
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int i = 0; i < NQ; ++i) fa[s][i] = fb[s][i] = g[s][i] = P[s][i] = Qv[s][i] = (C)0;
-    double r1m[2] = {0.0, 0.0}, r1c[2] = {0.0, 0.0};   // rho(t) of rows a - DIR, a
-    double r2m[2] = {0.0, 0.0}, r2c[2] = {0.0, 0.0};   // rho(t+1) of rows q - DIR, q
+        for (int i = 0; i < NQ; ++i) {
+            fa[s][i] = fb[s][i] = (C)0;
+#pragma unroll
+            for (int j = 0; j < NK; ++j) g[j][s][i] = P[j][s][i] = Qv[j][s][i] = (C)0;
+        }
+    // rm[j], rc[j]: densities after j steps of the rows behind and at the
+    // row stage j + 1 collides next
+    double rm[NS][2], rc[NS][2];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) rm[j][0] = rm[j][1] = rc[j][0] = rc[j][1] = 0.0;
 
     const int first = DIR > 0 ? y0 : y0 + nrows - 1;
-    const int a0 = first - 2 * DIR;
-    // prologue: densities of row a0 - DIR, row a0 in full, row a0 + DIR requested
+    const int a0 = first - 2 * (NS - 1) * DIR;
     if (inside(a0 - DIR)) {
         C hf[2][NQ];
         pull_site<ST, BCY>(src, M, wrap(a0 - DIR), c, hf);
-        r1m[0] = density(hf[0]);
-        r1m[1] = density(hf[1]);
+        rm[0][0] = density(hf[0]);
+        rm[0][1] = density(hf[1]);
     }
     if (inside(a0)) {
         pull_site<ST, BCY>(src, M, wrap(a0), c, fa);
-        r1c[0] = density(fa[0]);
-        r1c[1] = density(fa[1]);
+        rc[0][0] = density(fa[0]);
+        rc[0][1] = density(fa[1]);
     }
     if (inside(a0 + DIR)) pull_site<ST, BCY>(src, M, wrap(a0 + DIR), c, fb);
+    const int K = nrows + 4 * (NS - 1);
 
-    // march steps: step-1 rows a0 .. a0 + (K - 1) DIR
-    const int K = nrows + 4;
-
-    // f1c: row a (then row a + 2 DIR); f1n: row a + DIR
-    auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
-        const int a = a0 + k * DIR;
-        const bool in_a = inside(a), in_am = inside(a - DIR), in_ap = inside(a + DIR);
-        // row a + 2 DIR is needed unless this is the last step-1 row
-        const bool load_next = k + 1 < K && inside(a + 2 * DIR);
-        // rho(t) of row a + DIR (its loads were issued one iteration ago)
-        const double r1n[2] = {density(f1n[0]), density(f1n[1])};
-        // --- step 1 at row a
-        C out1[2][NQ];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) out1[s][i] = (C)0;
-        if (in_a) {
-            // beyond a wall psi is the wall row's (mirror) or zero
-            double rb[2], rf[2];
+    auto sums = [&](const double (&rb)[2], const double (&rcur)[2], const double (&rf)[2], double (&Sx)[2],
+                    double (&Sy)[2]) {
+        if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, rcur, rf, Sx, Sy);
+        else sc_sums_lanes<ST != ST_F64, ZF>(rf, rcur, rb, Sx, Sy);
+    };
+    auto collide_keep = [&](const C (&f)[2][NQ], const double (&rho)[2], const double (&Sx)[2], const double (&Sy)[2],
+                            int row, C (&out)[2][NQ]) {
+        collide_site<ST, FORCING>(M, f, rho, Sx, Sy, wall_row<BCY>(M, row), [&](int s, int i, C post) {
+            if constexpr (Q::SITE) out[s][i] = post;
+            else out[s][i] = Q::dec(Q::enc(post));
+        });
+        if constexpr (Q::SITE) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                rb[s] = in_am ? r1m[s] : (pz ? 0.0 : r1c[s]);
-                rf[s] = in_ap ? r1n[s] : (pz ? 0.0 : r1c[s]);
-            }
-            double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, r1c, rf, Sx, Sy);
-            else sc_sums_lanes<ST != ST_F64, ZF>(rf, r1c, rb, Sx, Sy);
-            collide_site<ST, FORCING>(M, f1c, r1c, Sx, Sy, wall_row<BCY>(M, a), [&](int s, int i, C post) {
-                if constexpr (Q::SITE) out1[s][i] = post;
-                else out1[s][i] = Q::dec(Q::enc(post));
-            });
-            if constexpr (Q::SITE) {
-                // the stored form, decoded as the next step pulls it
+                typename Q::T qc[NQ];
+                float rhat;
+                site_encode<ST>(M, rho[s], out[s], qc, rhat);
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    typename Q::T q[NQ];
-                    float rhat;
-                    site_encode<ST>(M, r1c[s], out1[s], q, rhat);
-#pragma unroll
-                    for (int i = 0; i < NQ; ++i) out1[s][i] = site_decode<ST>(M, q[i], rhat, i);
-                }
+                for (int i = 0; i < NQ; ++i) out[s][i] = site_decode<ST>(M, qc[i], rhat, i);
             }
-        } else if (BCY != BC_PERIODIC) {
-            // row a lies beyond a wall: the pull of row a - DIR takes its
-            // c_y = -DIR populations from its own reversed ones (bounce-back)
+        }
+    };
+    auto pull_rows = [&](int s, const C (&Qr)[2][NQ], const C (&Pr)[2][NQ], const C (&Or)[2][NQ], bool bbf, bool bbb,
+                         C (&v)[NQ]) {
+        v[0] = Pr[s][0];
+        v[1] = shift_x<1, ZF>(Pr[s][1]);
+        v[3] = shift_x<3, ZF>(Pr[s][3]);
+        v[FW[0]] = Qr[s][FW[0]];
+        v[FW[1]] = bbf ? Qr[s][FW[1]] : shift_x<FW[1], ZF>(Qr[s][FW[1]]);
+        v[FW[2]] = bbf ? Qr[s][FW[2]] : shift_x<FW[2], ZF>(Qr[s][FW[2]]);
+        v[BW[0]] = Or[s][BW[0]];
+        v[BW[1]] = bbb ? Or[s][BW[1]] : shift_x<BW[1], ZF>(Or[s][BW[1]]);
+        v[BW[2]] = bbb ? Or[s][BW[2]] : shift_x<BW[2], ZF>(Or[s][BW[2]]);
+    };
+    auto beyond = [&](bool in, const double (&r)[2], const double (&wall)[2], double (&out)[2]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) out[s] = in ? r[s] : (pz ? 0.0 : wall[s]);
+    };
+    auto rotate = [&](C (&Pr)[2][NQ], C (&Qr)[2][NQ], const C (&out)[2][NQ], bool bb_next) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Qr[s][FW[j]] = bb_next ? out[s][opp(FW[j])] : Pr[s][FW[j]];
+            Pr[s][0] = out[s][0];
+            Pr[s][1] = out[s][1];
+            Pr[s][3] = out[s][3];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Pr[s][FW[j]] = out[s][FW[j]];
+        }
+    };
+
+    auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
+        const int a = a0 + k * DIR;
+        const bool load_next = k + 1 < K && inside(a + 2 * DIR);
+        double rn[NS][2];           // densities after j steps of the row stage j + 1 pulls now
+        rn[0][0] = density(f1n[0]);
+        rn[0][1] = density(f1n[1]);
+        C out[NK][2][NQ];           // this iteration's results of the kept stages
+#pragma unroll
+        for (int j = 0; j < NK; ++j)
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) out1[s][BW[j]] = P[s][opp(BW[j])];
+                for (int i = 0; i < NQ; ++i) out[j][s][i] = (C)0;
+        // --- stage 1 at row a
+        if (inside(a)) {
+            double rb[2], rf[2], Sx[2], Sy[2];
+            beyond(inside(a - DIR), rm[0], rc[0], rb);
+            beyond(inside(a + DIR), rn[0], rc[0], rf);
+            sums(rb, rc[0], rf, Sx, Sy);
+            collide_keep(f1c, rc[0], Sx, Sy, a, out[0]);
+        } else if (BCY != BC_PERIODIC) {
+            // beyond a wall: the pull of the row behind takes its c_y = -DIR
+            // populations from its own reversed ones (bounce-back)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) out[0][s][BW[j]] = P[0][s][opp(BW[j])];
         }
-        // request row a + 2 DIR into the registers just freed
         if (load_next) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
-        // --- step 2: row p = a - DIR is pulled from the step-1 rows
-        const int p = a - DIR;
-        const bool pull_p = k >= 2 && inside(p);
-        const bool bb_f = (BCY != BC_PERIODIC) && !inside(p - DIR);   // Qv holds bounce-back values
-        const bool bb_b = (BCY != BC_PERIODIC) && !in_a;              // out1 holds bounce-back values
-        auto pull_row = [&](int s, C (&v)[NQ]) {
-            v[0] = P[s][0];
-            v[1] = shift_x<1, ZF>(P[s][1]);
-            v[3] = shift_x<3, ZF>(P[s][3]);
-            v[FW[0]] = Qv[s][FW[0]];
-            v[FW[1]] = bb_f ? Qv[s][FW[1]] : shift_x<FW[1], ZF>(Qv[s][FW[1]]);
-            v[FW[2]] = bb_f ? Qv[s][FW[2]] : shift_x<FW[2], ZF>(Qv[s][FW[2]]);
-            v[BW[0]] = out1[s][BW[0]];
-            v[BW[1]] = bb_b ? out1[s][BW[1]] : shift_x<BW[1], ZF>(out1[s][BW[1]]);
-            v[BW[2]] = bb_b ? out1[s][BW[2]] : shift_x<BW[2], ZF>(out1[s][BW[2]]);
-        };
-        // densities of row p (its populations are rebuilt after the
-        // collision of row q)
-        double r2n[2] = {0.0, 0.0};
-        if (pull_p) {
+        // --- stages 2 .. NS
+#pragma unroll
+        for (int j = 2; j <= NS; ++j) {
+            const int p = a - (2 * j - 3) * DIR;     // the row stage j pulls now
+            const int q = a - 2 * (j - 1) * DIR;     // the row stage j collides now
+            const bool pull = k >= 4 * j - 6 && inside(p);
+            const bool bbf = (BCY != BC_PERIODIC) && !inside(p - DIR);
+            const bool bbb = (BCY != BC_PERIODIC) && !inside(p + DIR);
+            rn[j - 1][0] = rn[j - 1][1] = 0.0;
+            if (pull) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    C v[NQ];
+                    pull_rows(s, Qv[j - 2], P[j - 2], out[j - 2], bbf, bbb, v);
+                    rn[j - 1][s] = density(v);
+                }
+            }
+            if (k >= 4 * (j - 1)) {
+                if (j < NS) {
+                    if (inside(q)) {
+                        double rb[2], rf[2], Sx[2], Sy[2];
+                        beyond(inside(q - DIR), rm[j - 1], rc[j - 1], rb);
+                        beyond(inside(p), rn[j - 1], rc[j - 1], rf);
+                        sums(rb, rc[j - 1], rf, Sx, Sy);
+                        collide_keep(g[j - 2], rc[j - 1], Sx, Sy, q, out[j - 1]);
+                    } else if (BCY != BC_PERIODIC) {
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) out[j - 1][s][BW[i]] = P[j - 1][s][opp(BW[i])];
+                    }
+                } else {
+                    // the last stage: row q lies inside the band
+                    double rb[2], rf[2], Sx[2], Sy[2];
+                    beyond(inside(q - DIR), rm[j - 1], rc[j - 1], rb);
+                    beyond(inside(p), rn[j - 1], rc[j - 1], rf);
+                    sums(rb, rc[j - 1], rf, Sx, Sy);
+                    const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
+                    if constexpr (Q::SITE) {
+                        C post[2][NQ];
+                        collide_site<ST, FORCING>(M, g[j - 2], rc[j - 1], Sx, Sy, wall_row<BCY>(M, q),
+                                                  [&](int s, int i, C pv) { post[s][i] = pv; });
+                        if (store_ok) store_site<ST>(M, wr, ox, c, wis, wss, rc[j - 1], post);
+                    } else {
+                        collide_site<ST, FORCING>(M, g[j - 2], rc[j - 1], Sx, Sy, wall_row<BCY>(M, q),
+                                                  [&](int s, int i, C post) {
+                            if (store_ok)
+                                bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox,
+                                                                    (unsigned)s * wss + (unsigned)i * wis);
+                        });
+                    }
+                }
+            }
+            if (pull) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) pull_rows(s, Qv[j - 2], P[j - 2], out[j - 2], bbf, bbb, g[j - 2][s]);
+            }
+        }
+        // --- rotate the kept stages' results and the densities
+#pragma unroll
+        for (int j = 1; j <= NK; ++j) {
+            const int q = a - 2 * (j - 1) * DIR;
+            rotate(P[j - 1], Qv[j - 1], out[j - 1], (BCY != BC_PERIODIC) && inside(q) && !inside(q - DIR));
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j)
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                C v[NQ];
-                pull_row(s, v);
-                r2n[s] = density(v);
+                rm[j][s] = rc[j][s];
+                rc[j][s] = rn[j][s];
             }
-        }
-        // --- step 2: collide row q = a - 2 DIR (inside the band from k = 4)
-        if (k >= 4) {
-            const int q = a - 2 * DIR;
-            double rb[2], rf[2];
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                rb[s] = inside(q - DIR) ? r2m[s] : (pz ? 0.0 : r2c[s]);
-                rf[s] = inside(p) ? r2n[s] : (pz ? 0.0 : r2c[s]);
-            }
-            double Sx[2], Sy[2];
-            if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, r2c, rf, Sx, Sy);
-            else sc_sums_lanes<ST != ST_F64, ZF>(rf, r2c, rb, Sx, Sy);
-            const rsrc_t wr = row_rsrc(dst, wrap(q), row_bytes);
-            if constexpr (Q::SITE) {
-                C post[2][NQ];
-                collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q),
-                                          [&](int s, int i, C p) { post[s][i] = p; });
-                if (store_ok) store_site<ST>(M, wr, ox, c, wis, wss, r2c, post);
-            } else {
-                collide_site<ST, FORCING>(M, g, r2c, Sx, Sy, wall_row<BCY>(M, q), [&](int s, int i, C post) {
-                    if (store_ok)
-                        bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
-                });
-            }
-        }
-        if (pull_p) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) pull_row(s, g[s]);
-        }
-        // --- rotate the step-1 results (row a becomes the previous row)
-        const bool bb_next = (BCY != BC_PERIODIC) && in_a && !in_am;   // row a is the first row at a wall
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Qv[s][FW[j]] = bb_next ? out1[s][opp(FW[j])] : P[s][FW[j]];
-            P[s][0] = out1[s][0];
-            P[s][1] = out1[s][1];
-            P[s][3] = out1[s][3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) P[s][FW[j]] = out1[s][FW[j]];
-        }
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            r1m[s] = r1c[s];
-            r1c[s] = r1n[s];
-            r2m[s] = r2c[s];
-            r2c[s] = r2n[s];
-        }
     };
     int k = 0;
     for (; k + 2 <= K; k += 2) {
@@ -1199,266 +1247,15 @@ k_step2(const Member *__restrict__ members, int n_members, int64_t item0, int64_
 #else
         const bool down = false;
 #endif
-        if (down) march2<ST, FORCING, BCY, -1>(M, cur, y0, nrows, c, store_ok);
-        else march2<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
+        if (down) marchN<ST, FORCING, BCY, -1, 2>(M, cur, y0, nrows, c, store_ok);
+        else marchN<ST, FORCING, BCY, 1, 2>(M, cur, y0, nrows, c, store_ok);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Three steps per pass: the march of the two-step pass with a third stage
-// behind the second.  Per march index k (step-1 row a = first - 4 DIR + k DIR):
-//   step 1 collides row a (rho(t) of a - DIR, a, a + DIR);
-//   step 2 pulls row a - DIR from the step-1 rows a - 2 DIR, a - DIR, a and
-//   collides row q = a - 2 DIR, whose results stay in registers;
-//   step 3 pulls row q - DIR from the step-2 rows q - 2 DIR, q - DIR, q and
-//   collides row r = a - 4 DIR, which it stores.
-// Steps 1 and 2 keep their results in the stored form (decoded as the next
-// pass would pull them), so the pass equals three single steps bit for bit.
-// A work item covers TX3 output columns (five lanes of halo on either side:
-// each step's pull and Eq. 5 sums reach one lane further) and a band of rows
-// whose f(t) rows extend five rows beyond it on either side.
-constexpr int TX3 = 54;
-
-template <int ST, int FORCING, int BCY, int DIR>
-__device__ __forceinline__ void march3(const Member &M, int cur, int y0, int nrows, int c, bool store_ok)
-{
-    using Q = Tr<ST>;
-    using T = typename Q::T;
-    using C = typename Q::C;
-    // zero-filling lane shifts in every mode: this pass is bound by its
-    // instruction issue, and the zero fill saves the copy of each shifted
-    // value (FP64 33.8 -> 37.1 GLUPS, FP32 66.9 -> 68.7 at 10000 x 5000)
-    constexpr bool ZF = true;
-    const int ny = M.ny;
-    const void *src = M.f[cur];
-    void *dst = M.f[cur ^ 1];
-    const int64_t row_bytes = M.ystride * (int64_t)sizeof(T);
-    const unsigned ox = (unsigned)c * (unsigned)sizeof(T);
-    const unsigned wis = (unsigned)M.istride * (unsigned)sizeof(T);
-    const unsigned wss = (unsigned)M.sstride * (unsigned)sizeof(T);
-    auto inside = [&](int v) { return BCY == BC_PERIODIC || (v >= 0 && v < ny); };
-    const bool pz = BCY == BC_WALLS_WET && M.psi_zero;
-    auto wrap = [&](int v) {
-        if (BCY == BC_PERIODIC) {
-            v %= ny;
-            if (v < 0) v += ny;
-        }
-        return v;
-    };
-    constexpr int FW[3] = {DIR > 0 ? 2 : 4, DIR > 0 ? 5 : 7, DIR > 0 ? 6 : 8};
-    constexpr int BW[3] = {DIR > 0 ? 4 : 2, DIR > 0 ? 7 : 5, DIR > 0 ? 8 : 6};
-
-    C fa[2][NQ], fb[2][NQ];     // pulled f(t) of rows a and a + DIR
-    C g[2][NQ];                 // pulled f(t+1) of row q (then of row a - DIR)
-    C hh[2][NQ];                // pulled f(t+2) of row r (then of row q - DIR)
-    C P[2][NQ], Qv[2][NQ];      // step-1 results of rows a - DIR (c_y = 0, DIR) and a - 2 DIR (c_y = DIR)
-    C P2[2][NQ], Qv2[2][NQ];    // step-2 results of rows q - DIR and q - 2 DIR
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < NQ; ++i)
-            fa[s][i] = fb[s][i] = g[s][i] = hh[s][i] = P[s][i] = Qv[s][i] = P2[s][i] = Qv2[s][i] = (C)0;
-    double r1m[2] = {0.0, 0.0}, r1c[2] = {0.0, 0.0};   // rho(t) of rows a - DIR, a
-    double r2m[2] = {0.0, 0.0}, r2c[2] = {0.0, 0.0};   // rho(t+1) of rows q - DIR, q
-    double r3m[2] = {0.0, 0.0}, r3c[2] = {0.0, 0.0};   // rho(t+2) of rows r - DIR, r
-
-    const int first = DIR > 0 ? y0 : y0 + nrows - 1;
-    const int a0 = first - 4 * DIR;
-    if (inside(a0 - DIR)) {
-        C hf[2][NQ];
-        pull_site<ST, BCY>(src, M, wrap(a0 - DIR), c, hf);
-        r1m[0] = density(hf[0]);
-        r1m[1] = density(hf[1]);
-    }
-    if (inside(a0)) {
-        pull_site<ST, BCY>(src, M, wrap(a0), c, fa);
-        r1c[0] = density(fa[0]);
-        r1c[1] = density(fa[1]);
-    }
-    if (inside(a0 + DIR)) pull_site<ST, BCY>(src, M, wrap(a0 + DIR), c, fb);
-    const int K = nrows + 8;
-
-    // Eq. 5 sums from the densities of the rows behind (rb), at (rc) and
-    // ahead of (rf) a row in the march
-    auto sums = [&](const double (&rb)[2], const double (&rc)[2], const double (&rf)[2], double (&Sx)[2],
-                    double (&Sy)[2]) {
-        if constexpr (DIR > 0) sc_sums_lanes<ST != ST_F64, ZF>(rb, rc, rf, Sx, Sy);
-        else sc_sums_lanes<ST != ST_F64, ZF>(rf, rc, rb, Sx, Sy);
-    };
-    // collision of a row whose results stay in registers, in the stored form
-    auto collide_keep = [&](const C (&f)[2][NQ], const double (&rho)[2], const double (&Sx)[2], const double (&Sy)[2],
-                            int row, C (&out)[2][NQ]) {
-        collide_site<ST, FORCING>(M, f, rho, Sx, Sy, wall_row<BCY>(M, row), [&](int s, int i, C post) {
-            if constexpr (Q::SITE) out[s][i] = post;
-            else out[s][i] = Q::dec(Q::enc(post));
-        });
-        if constexpr (Q::SITE) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                typename Q::T qc[NQ];
-                float rhat;
-                site_encode<ST>(M, rho[s], out[s], qc, rhat);
-#pragma unroll
-                for (int i = 0; i < NQ; ++i) out[s][i] = site_decode<ST>(M, qc[i], rhat, i);
-            }
-        }
-    };
-    // pull of a row from rows of results: Qr the row behind (its c_y = DIR
-    // populations), Pr the row itself (c_y = 0), Or the row ahead (c_y = -DIR);
-    // bounce-back values (bbf: Qr holds them, bbb: Or holds them) are not shifted
-    auto pull_rows = [&](int s, const C (&Qr)[2][NQ], const C (&Pr)[2][NQ], const C (&Or)[2][NQ], bool bbf, bool bbb,
-                         C (&v)[NQ]) {
-        v[0] = Pr[s][0];
-        v[1] = shift_x<1, ZF>(Pr[s][1]);
-        v[3] = shift_x<3, ZF>(Pr[s][3]);
-        v[FW[0]] = Qr[s][FW[0]];
-        v[FW[1]] = bbf ? Qr[s][FW[1]] : shift_x<FW[1], ZF>(Qr[s][FW[1]]);
-        v[FW[2]] = bbf ? Qr[s][FW[2]] : shift_x<FW[2], ZF>(Qr[s][FW[2]]);
-        v[BW[0]] = Or[s][BW[0]];
-        v[BW[1]] = bbb ? Or[s][BW[1]] : shift_x<BW[1], ZF>(Or[s][BW[1]]);
-        v[BW[2]] = bbb ? Or[s][BW[2]] : shift_x<BW[2], ZF>(Or[s][BW[2]]);
-    };
-    // beyond a wall psi is the wall row's (mirror) or zero
-    auto beyond = [&](bool in, const double (&r)[2], const double (&wall)[2], double (&out)[2]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) out[s] = in ? r[s] : (pz ? 0.0 : wall[s]);
-    };
-    // rotate a stage's results: row x becomes the row behind the next pull
-    auto rotate = [&](C (&Pr)[2][NQ], C (&Qr)[2][NQ], const C (&out)[2][NQ], bool bb_next) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Qr[s][FW[j]] = bb_next ? out[s][opp(FW[j])] : Pr[s][FW[j]];
-            Pr[s][0] = out[s][0];
-            Pr[s][1] = out[s][1];
-            Pr[s][3] = out[s][3];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) Pr[s][FW[j]] = out[s][FW[j]];
-        }
-    };
-
-    auto iter = [&](int k, C (&f1c)[2][NQ], C (&f1n)[2][NQ]) {
-        const int a = a0 + k * DIR;
-        const bool in_a = inside(a), in_am = inside(a - DIR), in_ap = inside(a + DIR);
-        const bool load_next = k + 1 < K && inside(a + 2 * DIR);
-        const double r1n[2] = {density(f1n[0]), density(f1n[1])};
-        // --- step 1 at row a
-        C out1[2][NQ];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) out1[s][i] = (C)0;
-        if (in_a) {
-            double rb[2], rf[2], Sx[2], Sy[2];
-            beyond(in_am, r1m, r1c, rb);
-            beyond(in_ap, r1n, r1c, rf);
-            sums(rb, r1c, rf, Sx, Sy);
-            collide_keep(f1c, r1c, Sx, Sy, a, out1);
-        } else if (BCY != BC_PERIODIC) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) out1[s][BW[j]] = P[s][opp(BW[j])];
-        }
-        if (load_next) pull_site<ST, BCY>(src, M, wrap(a + 2 * DIR), c, f1c);
-        // --- step 2: row p = a - DIR pulled from the step-1 rows
-        const int p = a - DIR;
-        const bool pull_p = k >= 2 && inside(p);
-        const bool bb_f = (BCY != BC_PERIODIC) && !inside(p - DIR);
-        const bool bb_b = (BCY != BC_PERIODIC) && !in_a;
-        double r2n[2] = {0.0, 0.0};
-        if (pull_p) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                C v[NQ];
-                pull_rows(s, Qv, P, out1, bb_f, bb_b, v);
-                r2n[s] = density(v);
-            }
-        }
-        // --- step 2 collides row q = a - 2 DIR (rows first - 2 DIR on)
-        const int q = a - 2 * DIR;
-        const bool in_q = inside(q);
-        C out2[2][NQ];
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int i = 0; i < NQ; ++i) out2[s][i] = (C)0;
-        if (k >= 4) {
-            if (in_q) {
-                double rb[2], rf[2], Sx[2], Sy[2];
-                beyond(inside(q - DIR), r2m, r2c, rb);
-                beyond(inside(p), r2n, r2c, rf);
-                sums(rb, r2c, rf, Sx, Sy);
-                collide_keep(g, r2c, Sx, Sy, q, out2);
-            } else if (BCY != BC_PERIODIC) {
-#pragma unroll
-                for (int s = 0; s < 2; ++s)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) out2[s][BW[j]] = P2[s][opp(BW[j])];
-            }
-        }
-        if (pull_p) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) pull_rows(s, Qv, P, out1, bb_f, bb_b, g[s]);
-        }
-        // --- step 3: row p3 = q - DIR pulled from the step-2 rows
-        const int p3 = q - DIR;
-        const bool pull_p3 = k >= 6 && inside(p3);
-        const bool bb3_f = (BCY != BC_PERIODIC) && !inside(p3 - DIR);
-        const bool bb3_b = (BCY != BC_PERIODIC) && !in_q;
-        double r3n[2] = {0.0, 0.0};
-        if (pull_p3) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                C v[NQ];
-                pull_rows(s, Qv2, P2, out2, bb3_f, bb3_b, v);
-                r3n[s] = density(v);
-            }
-        }
-        // --- step 3 collides and stores row r = a - 4 DIR (inside the band from k = 8)
-        if (k >= 8) {
-            const int r = a - 4 * DIR;
-            double rb[2], rf[2], Sx[2], Sy[2];
-            beyond(inside(r - DIR), r3m, r3c, rb);
-            beyond(inside(p3), r3n, r3c, rf);
-            sums(rb, r3c, rf, Sx, Sy);
-            const rsrc_t wr = row_rsrc(dst, wrap(r), row_bytes);
-            if constexpr (Q::SITE) {
-                C post[2][NQ];
-                collide_site<ST, FORCING>(M, hh, r3c, Sx, Sy, wall_row<BCY>(M, r),
-                                          [&](int s, int i, C pv) { post[s][i] = pv; });
-                if (store_ok) store_site<ST>(M, wr, ox, c, wis, wss, r3c, post);
-            } else {
-                collide_site<ST, FORCING>(M, hh, r3c, Sx, Sy, wall_row<BCY>(M, r), [&](int s, int i, C post) {
-                    if (store_ok)
-                        bstore<LBK_NT_STORE ? CPOL_NT : 0>(Q::enc(post), wr, ox, (unsigned)s * wss + (unsigned)i * wis);
-                });
-            }
-        }
-        if (pull_p3) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) pull_rows(s, Qv2, P2, out2, bb3_f, bb3_b, hh[s]);
-        }
-        // --- rotate both stages' results and the densities
-        rotate(P, Qv, out1, (BCY != BC_PERIODIC) && in_a && !in_am);
-        rotate(P2, Qv2, out2, (BCY != BC_PERIODIC) && in_q && !inside(q - DIR));
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            r1m[s] = r1c[s];
-            r1c[s] = r1n[s];
-            r2m[s] = r2c[s];
-            r2c[s] = r2n[s];
-            r3m[s] = r3c[s];
-            r3c[s] = r3n[s];
-        }
-    };
-    int k = 0;
-    for (; k + 2 <= K; k += 2) {
-        iter(k, fa, fb);
-        iter(k + 1, fb, fa);
-    }
-    if (k < K) iter(k, fa, fb);
-}
+// Three steps per pass: the march with a third stage (54 output columns per
+// wave, ten extra f(t) rows per band).
+constexpr int TX3 = tx_of_pass<3>();
 
 // FP32 arithmetic: about 210 VGPRs, two waves per SIMD.  FP64: the two sets
 // of pulled rows and two stages of results need about 350 registers, so the
@@ -1494,10 +1291,10 @@ k_step3(const Member *__restrict__ members, int n_members, int64_t item0, int64_
             // neighbouring bands share halo rows in the caches gains less
             // (measured 3 % faster without it at 10000 x 5000)
             (void)ty;
-            march3<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
+            marchN<ST, FORCING, BCY, 1, 3>(M, cur, y0, nrows, c, store_ok);
         } else {
-            if ((ty & 1) != 0) march3<ST, FORCING, BCY, -1>(M, cur, y0, nrows, c, store_ok);
-            else march3<ST, FORCING, BCY, 1>(M, cur, y0, nrows, c, store_ok);
+            if ((ty & 1) != 0) marchN<ST, FORCING, BCY, -1, 3>(M, cur, y0, nrows, c, store_ok);
+            else marchN<ST, FORCING, BCY, 1, 3>(M, cur, y0, nrows, c, store_ok);
         }
     }
 }
