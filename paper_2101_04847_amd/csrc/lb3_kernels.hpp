@@ -72,19 +72,25 @@ struct Fields3 {
     double *rhoA, *rhoB, *ux, *uy, *uz;   // [nz][ny][nx], any may be null
 };
 
+// Column offset of a lane that pulls nothing: beyond every row's extent, so
+// its buffer loads return zero without a memory access.
+constexpr unsigned NO_COLUMN = 0x80000000u;
+
 // Pull the 38 populations of site (x, y, z) from the post-collision buffer.
 // The values land in f as V: the storage type itself (kept in registers by
 // the fused pass) or double (converted on load; the conversion is exact).
+// A lane with live false loads nothing and gets zeros.
 template <int ST, int BCY, class V>
-__device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int y, int x, V (&f)[2][NQ3])
+__device__ __forceinline__ void pull3(const void *src, const Lat3 &L, int z, int y, int x, V (&f)[2][NQ3],
+                                      bool live = true)
 {
     using T = typename Tr<ST>::T;
     const int64_t row_bytes = L.rstride * (int64_t)sizeof(T);
     const unsigned is = (unsigned)L.pitch * (unsigned)sizeof(T);
     const unsigned ss = (unsigned)NQ3 * is;
-    const unsigned oc = (unsigned)x * (unsigned)sizeof(T);
-    const unsigned om = (unsigned)(x == 0 ? L.nx - 1 : x - 1) * (unsigned)sizeof(T);    // source of c_x = +1
-    const unsigned op = (unsigned)(x == L.nx - 1 ? 0 : x + 1) * (unsigned)sizeof(T);    // source of c_x = -1
+    const unsigned oc = live ? (unsigned)x * (unsigned)sizeof(T) : NO_COLUMN;
+    const unsigned om = live ? (unsigned)(x == 0 ? L.nx - 1 : x - 1) * (unsigned)sizeof(T) : NO_COLUMN;   // c_x = +1
+    const unsigned op = live ? (unsigned)(x == L.nx - 1 ? 0 : x + 1) * (unsigned)sizeof(T) : NO_COLUMN;   // c_x = -1
 #pragma unroll
     for (int i = 0; i < NQ3; ++i) {
         int ys = y - c3y(i), zs = z - c3z(i);
@@ -342,12 +348,15 @@ __global__ void __launch_bounds__(FX * FY) k3_fused(Lat3 L, int cur, int nzb)
         ys = ys < 0 ? 0 : (ys >= L.ny ? L.ny - 1 : ys);
     }
     const bool interior = lane >= 1 && lane <= FX - 2 && ty >= 1 && ty <= FY - 2 && xu < L.nx && yu < L.ny;
+    // lanes beyond the one-site halo of the lattice's last column or row
+    // (the spare width of the last tile) pull nothing
+    const bool live = xu <= L.nx && yu <= L.ny;
     const void *src = L.f[cur];
     // pull plane zp of this thread's site into f and its densities into a ring slot
     auto pull_plane = [&](int zp, V (&f)[2][NQ3], int slot) {
         zp %= L.nz;
         if (zp < 0) zp += L.nz;
-        pull3<ST, BCY>(src, L, zp, ys, xs, f);
+        pull3<ST, BCY>(src, L, zp, ys, xs, f, live);
         ring[slot][0][ty][lane] = density3(f[0]);
         ring[slot][1][ty][lane] = density3(f[1]);
     };
