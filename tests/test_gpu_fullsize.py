@@ -50,9 +50,10 @@ def _bound(states, rows, storage, scale):
 
 @pytest.mark.timeout(900)
 def test_production_size():
-    """FP64 in the benchmark's launch configuration with a graph of 10 steps
-    (5 fused passes) replayed once and one more single step: every density
-    and velocity after 11 steps against the oracle.  Then FP32 (fused pass),
+    """FP64 in the benchmark's launch configuration (the pass and band of the
+    timing search) with a graph of 10 steps (three three-step passes and a
+    single step) replayed once and one more single step: every density and
+    velocity after 11 steps against the oracle.  Then FP32 (fused pass),
     FP16S and BF16S (single step, 256-column tiles) in their timed
     configurations after three steps, each within its rounding bound."""
     import torch
