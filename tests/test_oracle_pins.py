@@ -167,6 +167,31 @@ def test_potential_energy_mass_and_buoyancy_closed_forms(orc):
     assert d["omega2"] == 0.0 and d["Ek"] == pytest.approx(np.mean(rho * (g * phi / (2 * rho)) ** 2 / 2), rel=1e-12)
 
 
+def test_hydrodynamic_velocity_of_a_forced_rest_state(orc):
+    """A uniform mixture at rest (j_A = j_B = 0) under body accelerations with
+    x and y components (G = 0, periodic y: no Shan-Chen and no wall force):
+    the total force is F = rho_A g_A + rho_B g_B, the hydrodynamic velocity
+    is half of it over the density, u_phys = F / (2 rho), in both
+    directions, and so E_k = rho |u_phys|^2 / 2, B = -<u_phys . F> =
+    -|F|^2 / (2 rho) and max |u| = |F| / (2 rho)."""
+    nx, ny = 9, 14
+    rA, rB = 0.7, 0.45
+    gA, gB = (3e-3, -2e-3), (-1e-3, 5e-3)
+    p = orc.Params(nx=nx, ny=ny, tau=(0.8, 1.1), G=0.0, g=(gA, gB), periodic_y=True)
+    f = orc.fill_equilibrium(p, np.full((ny, nx), rA), np.full((ny, nx), rB))
+    m = orc.macro(p, f)
+    rho = rA + rB
+    Fx, Fy = rA * gA[0] + rB * gB[0], rA * gA[1] + rB * gB[1]
+    assert np.max(np.abs(m["Fx"] - Fx)) <= 1e-16 and np.max(np.abs(m["Fy"] - Fy)) <= 1e-16
+    assert np.max(np.abs(m["ux"] - Fx / (2 * rho))) <= 1e-16
+    assert np.max(np.abs(m["uy"] - Fy / (2 * rho))) <= 1e-16
+    d = orc.diagnostics(p, f, trim=2)
+    u2 = (Fx * Fx + Fy * Fy) / (2 * rho) ** 2
+    assert d["Ek"] == pytest.approx(0.5 * rho * u2, rel=1e-12)
+    assert d["buoyancy"] == pytest.approx(-(Fx * Fx + Fy * Fy) / (2 * rho), rel=1e-12)
+    assert d["umax"] == pytest.approx(np.sqrt(u2), rel=1e-14)
+
+
 @pytest.mark.parametrize("n,N", [(1, 32), (3, 48)])
 def test_enstrophy_and_kinetic_energy_taylor_green(orc, n, N):
     """Eq. 22 reduction on a Taylor-Green field u = U (sin kx cos ky,
