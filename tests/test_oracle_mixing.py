@@ -66,7 +66,9 @@ def test_reference_rows_and_asymmetric_phases():
     every row of the lower phase 6 c (1 - c) = 0.154."""
     trim, ny = 10, 80
     prof = [-0.9] * (ny // 2) + [1.0] * (ny // 2)
-    prof[0] = prof[-1] = 7.0
+    # every trimmed row (the ones next to D included) holds another value
+    for j in list(range(trim)) + list(range(ny - trim, ny)):
+        prof[j] = 7.0 + j
     lo, hi = mixing.bulk_reference(prof, trim)
     assert (lo, hi) == (-0.9, 1.0)
     assert mixing.mixing_width(prof, lo, hi, trim) == 0.0
