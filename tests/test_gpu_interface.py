@@ -45,6 +45,26 @@ def test_interface_counts_match_oracle(lb, nx, ny, trim, G, steps):
     lat.close()
 
 
+def test_sites_with_phi_zero_belong_to_b(lb):
+    """Exact zeros of phi (rho_A = rho_B at rest) count as the B phase, as in
+    the oracle: a checkerboard of phi = 0 and phi = 0.4 crosses on every row
+    and column pair and on no diagonal pair."""
+    import numpy as np
+    print("[case] interface, phi = 0 checkerboard", flush=True)
+    nx, ny, trim = 64, 20, 2
+    y, x = np.mgrid[0:ny, 0:nx]
+    rA = np.where((x + y) % 2 == 1, 0.95, 0.55)
+    rB = np.full((ny, nx), 0.55)
+    lat = lb.Lattice([lb.Member(nx, ny, rA, rB)], tile_x=64, tile_h=16, graph_chunk=-1, diag_trim=trim)
+    p = oracle.Params(nx=nx, ny=ny)
+    f = oracle.fill_equilibrium(p, rA, rB)
+    got = lat.interface_length(0)
+    m = ny - 2 * trim
+    assert (got["n0"], got["n90"], got["n45"], got["n135"]) == (nx * m, nx * (m - 1), 0, 0)
+    _check(got, p, f, trim)
+    lat.close()
+
+
 def test_interface_medium_timed_configuration(lb):
     wl = inputs.MEDIUM_2048x1024
     print("[case] interface", wl.name, flush=True)

@@ -51,6 +51,22 @@ def test_known_shapes(lb):
     lat.close()
 
 
+def test_sites_with_phi_zero_belong_to_b(lb):
+    """Exact zeros of phi (rho_A = rho_B at rest) count as the B phase, as in
+    the oracle: on a checkerboard of phi = 0 and phi = 0.4 every site of D is
+    its own 4-connected component."""
+    print("[case] phi = 0 checkerboard", flush=True)
+    nx, ny, trim = 64, 20, 2
+    y, x = np.mgrid[0:ny, 0:nx]
+    phi = np.where((x + y) % 2 == 1, 0.4, 0.0)
+    lat, p, f = _lattice_from_phi(lb, phi, trim)
+    got = lat.components(0)
+    half = nx * (ny - 2 * trim) // 2
+    assert (got["A"], got["B"]) == (half, half)
+    _check(got, p, f, trim)
+    lat.close()
+
+
 @pytest.mark.parametrize("nx,ny,frac,seed", [(64, 40, 0.5, 1), (257, 130, 0.45, 2), (1000, 600, 0.55, 3),
                                              (2048, 1024, 0.5, 4)])
 def test_random_masks(lb, nx, ny, frac, seed):

@@ -37,6 +37,18 @@ def test_flat_interface_counts_and_length():
     assert out["length"] == np.pi / 8 * (nx + 2 * nx / np.sqrt(2))
 
 
+def test_sites_with_phi_zero_belong_to_the_b_phase():
+    """A site is in the A phase where phi > 0 strictly: on a checkerboard of
+    phi = 0 and phi = 1 every row and column pair crosses and no diagonal
+    pair does (counting phi = 0 as A would see no interface at all)."""
+    nx, ny, trim = 8, 12, 2
+    y, x = np.mgrid[0:ny, 0:nx]
+    phi = ((x + y) % 2).astype(np.float64)
+    c = interface.crossing_counts(phi, trim)
+    m = ny - 2 * trim
+    assert (c["n0"], c["n90"], c["n45"], c["n135"]) == (nx * m, nx * (m - 1), 0, 0)
+
+
 def test_circle_length():
     """The four directions sample theta exactly for a circle (its crossing
     integral is 4R at every angle), so only the line spacing errs."""

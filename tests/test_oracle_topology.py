@@ -58,3 +58,6 @@ def test_known_shapes():
     m = ((x[:, :8] + y[:8]) % 2) == 0
     a, b = _fields(m, 1)
     assert topology.component_counts(a, b, 1) == {"A": 32, "B": 32}
+    # sites with phi = 0 exactly (rho_A = rho_B) belong to the B phase
+    a0, b0 = np.where(a > 0.5, 1.0, 0.5), np.full_like(a, 0.5)
+    assert topology.component_counts(a0, b0, 1) == {"A": 32, "B": 32}
