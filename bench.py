@@ -266,7 +266,7 @@ def variant_line(lb, inputs, name, stream, steps=300, warmup=50, spp=0, **walls)
     sites = wl.nx * wl.ny
     mlups = sites / (ms / 1e3) / 1e6
     out = {"storage": name, "MLUPS": round(mlups, 1), "ms_per_step": round(ms, 4), "steps_per_pass": got,
-           "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": BYTES_PER_LU[name] // got,
+           "kernel": "lbk::k_" + KERNEL[got], "tile": list(tile), "bytes_per_lu": round(BYTES_PER_LU[name] / got, 2),
            "hbm_frac": hbm_frac(name, got, ms, sites),
            "hbm_frac_single_step_basis": hbm_frac_single_step_basis(name, ms, sites)}
     if walls:
@@ -593,7 +593,7 @@ def main() -> int:
     copy = copy_bandwidth(stream)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "bytes_per_launch": alg_bytes, "bytes_per_lu": BYTES_PER_LU[args.storage] // spp,
+            "bytes_per_launch": alg_bytes, "bytes_per_lu": round(BYTES_PER_LU[args.storage] / spp, 2),
             "kernel": "lbk::k_" + kernel, "steps_per_launch": spp, "launch_ms": round(launch_ms, 4),
             # counted HBM-side bytes over the algorithmic bytes of one launch
             "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),

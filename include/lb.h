@@ -312,9 +312,10 @@ int32_t lb_steps_per_pass(const lb_handle *h);
 
 /* 1 if lb_init took the pass and tile shapes from the persisted tile cache,
  * 0 if it timed them (or they were given), negative: error code.  The cache
- * is a JSON file keyed by the device (architecture, compute units), storage,
- * forcing, boundary variant, the requested steps_per_pass / tile_x / tile_h
- * and every member's nx, ny: the environment variable LB_TILE_CACHE names
+ * is a JSON file keyed by the device (architecture, compute units), the
+ * version of the search, storage, forcing, boundary variant, the requested
+ * steps_per_pass / tile_x / tile_h and every member's nx, ny: the
+ * environment variable LB_TILE_CACHE names
  * it ("off" or empty: no cache), by default $XDG_CACHE_HOME/liblb/tiles.json
  * or $HOME/.cache/liblb/tiles.json.  A choice that is timed is recorded
  * there; a cached choice gives the same results bit for bit (tile shapes

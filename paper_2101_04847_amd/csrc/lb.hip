@@ -664,6 +664,37 @@ int32_t search_tiles(lb_handle *h)
         float best3 = 1e30f;
         if (c.tile_h == 0 || spp == 0) {
             std::vector<int> heights = {8, 12, 16, 24, 32, 48, 64, 96, 128, 160};
+            // Heights that fill whole rounds of the GPU's wave slots: each work
+            // item is one wave, the FP64 pass runs one wave per SIMD and the
+            // others two, so S = CUs x 4 (x 2) items run at once.  With n items
+            // per row of bands, a height h takes r = ceil(nb n / S) rounds for
+            // its nb = ceil(ny / h) bands; the most bands that fit those rounds,
+            // floor(r S / n), of ceil(ny / that) rows each, leave none of the
+            // last round idle.  Tall bands feel it most (10000 x 5000 FP64:
+            // 37.9 GLUPS at 160 rows, 39.5-40.3 at the filled 455, 313, 228,
+            // 186 and 152).  Every candidate, and a few taller ones, gets its
+            // filled height as a candidate too; one size class only (mixed
+            // sizes share rounds).
+            if (shapes.size() == 1) {
+                int cus = 0;
+                if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
+                    cus = 0;
+                const int64_t slots = (int64_t)cus * 4 * (c.storage == LB_F64 ? 1 : 2);
+                const int64_t per_band = (int64_t)nm * ((shapes[0].first + TX3 - 1) / TX3);
+                const int64_t ny3 = shapes[0].second;
+                std::vector<int> from = heights;
+                for (int tall : {192, 256, 320, 384, 512}) from.push_back(tall);
+                for (int hgt : from) {
+                    if (slots <= 0) break;
+                    const int64_t nb = (ny3 + hgt - 1) / hgt;
+                    const int64_t r = (nb * per_band + slots - 1) / slots;
+                    const int64_t nbf = r * slots / per_band;
+                    if (nbf < 1) continue;
+                    const int hf = (int)((ny3 + nbf - 1) / nbf);
+                    if (hf >= 8 && hf <= 512 && std::find(heights.begin(), heights.end(), hf) == heights.end())
+                        heights.push_back(hf);
+                }
+            }
             if (c.tile_h > 0) heights = {c.tile_h};
             int32_t rc = search(heights, 24, [&](const std::vector<int> &thm, float &t) {
                 return time_shape3(h, thm, reps, t);
@@ -701,7 +732,8 @@ std::string tune_key(const lb_handle *h)
         cus = prop.multiProcessorCount;
     }
     const lb_config &c = h->cfg;
-    std::string k = arch + "|cu" + std::to_string(cus) + "|st" + std::to_string(c.storage) + "|f" +
+    // s2: the search with the round-filling band heights of the three-step pass
+    std::string k = arch + "|cu" + std::to_string(cus) + "|s2|st" + std::to_string(c.storage) + "|f" +
                     std::to_string(c.forcing) + "|bc" + std::to_string(h->kbc) + "|spp" +
                     std::to_string(c.steps_per_pass) + "|tx" + std::to_string(c.tile_x) + "|th" +
                     std::to_string(c.tile_h) + "|";
