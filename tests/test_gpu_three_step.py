@@ -90,6 +90,23 @@ def test_three_step_ragged_bands_and_narrow_lattices(lb, storage, bc):
             three.close()
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16s"])
+@pytest.mark.parametrize("band", [228, 455])
+def test_three_step_tall_bands(lb, storage, band):
+    """Bands as tall as the timing search picks at 10000 x 5000 (the heights
+    that fill whole rounds of the wave slots), on a lattice of 1000 rows: a
+    march of band + 10 rows per work item, and a ragged last band."""
+    _say("three-step tall band", storage, band)
+    m = _member(lb, 130, 1000, seed=7, G=1.3)
+    one, three = _pair(lb, [m], ST[storage], band=band, chunk3=6)
+    for n in (3, 7, 12):
+        one.step(n)
+        three.step(n)
+        assert _same(one, three), (band, n)
+    one.close()
+    three.close()
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("forcing", [0, 1], ids=["shift", "guo"])
 @pytest.mark.parametrize("wall_psi,G_wall", [(0, (0.12, -0.08)), (1, (0.3, 0.05))], ids=["mirror", "zero"])
