@@ -167,6 +167,29 @@ def test_potential_energy_mass_and_buoyancy_closed_forms(orc):
     assert d["omega2"] == 0.0 and d["Ek"] == pytest.approx(np.mean(rho * (g * phi / (2 * rho)) ** 2 / 2), rel=1e-12)
 
 
+def test_each_component_relaxes_at_its_own_rate(orc):
+    """Eq. 2 with tau_A != tau_B on a uniform mixture at rest (G = 0, g = 0,
+    periodic y, so streaming maps the uniform state onto itself): a
+    departure from equilibrium that carries no mass and no momentum (+e on
+    the two x links, -e on the two y links) leaves rho and u, hence f^eq,
+    unchanged, and decays by the factor 1 - 1/tau_s per step in component s."""
+    nx, ny, e = 6, 5, 1e-3
+    tau = (0.8, 1.7)
+    p = orc.Params(nx=nx, ny=ny, tau=tau, periodic_y=True)
+    f0 = orc.fill_equilibrium(p, np.full((ny, nx), 0.7), np.full((ny, nx), 0.4))
+    cx, cy, _, _ = orc.constants()
+    d = np.zeros_like(f0)
+    for i in range(9):
+        if cx[i] != 0 and cy[i] == 0:
+            d[:, i] = e
+        elif cy[i] != 0 and cx[i] == 0:
+            d[:, i] = -e
+    f1 = orc.step(p, f0 + d)
+    for s in range(2):
+        want = f0[s] + (1.0 - 1.0 / tau[s]) * d[s]
+        assert np.max(np.abs(f1[s] - want)) <= 1e-15, s
+
+
 def test_hydrodynamic_velocity_of_a_forced_rest_state(orc):
     """A uniform mixture at rest (j_A = j_B = 0) under body accelerations with
     x and y components (G = 0, periodic y: no Shan-Chen and no wall force):
