@@ -18,8 +18,8 @@ on a bounded sample of the same workload, the reduced-precision storage
 modes, and the 16-member batched ensemble (4 x 1024x512, 8 x 2048x1024,
 4 x 4096x2048, FP32).
 
-Besides the rates, the line carries the measurements the rates are judged
-by: the density-field error of FP32 storage against FP64 on the headline
+Besides the rates, the line carries the measurements that qualify them:
+the density-field error of FP32 storage against FP64 on the headline
 lattice at step 2000; mass drift, mixing-width and density errors of the
 reduced-precision codes on the 4096 x 2048 lattices (miscible and
 immiscible) over 20000 steps against FP64; the 16 ensemble members' errors
